@@ -1,0 +1,168 @@
+#!/usr/bin/env python3
+"""Throughput of the ion-flow step on one MI355X.
+
+Workload: two 5 um grains on the axis 0.5 r_De apart, Mach 1 argon flow with
+charge exchange (nu = 0.1 omega_pi), N = 2^20 ion superparticles in a
+cylinder of radius 3 r_De and height 8 r_De, dt = 0.01/omega_pi; synthetic,
+seeded initial state.  A step is the whole hot path: all-pairs forces, push
+with collisions/absorption/exit/reinjection, charge and force bookkeeping.
+
+Prints one JSON line: ion-steps/s (value), pair interactions/s, the FP32
+roofline fraction of the pair kernel (per-launch HIP-event time), the HBM
+rate of the push kernel, and the FP64 CPU oracle timed on a bounded sample of
+the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOP_PER_PAIR = 23            # algorithmic FP32 flop per ordered pair
+PEAK_FP32 = 157.3e12          # MI355X published FP32 vector peak (counts packed FP32)
+PEAK_HBM = 8.0e12             # MI355X HBM3E, B/s
+
+
+def push_bytes_per_ion(prec: int) -> int:
+    e = 4 if prec == 0 else 8
+    return 3 * e * 3 + 2 * 3 * e + 1      # read x, v, a; write x, v; write event byte
+
+
+def cpu_baseline(w, sysm, target_s: float):
+    """The FP64 oracle's force evaluation on a sample of target ions of the
+    same 2^20-ion state (every ion a source), scaled to ion-steps/s."""
+    import numpy as np
+    from oracle import oracle as O
+    o = O.Oracle(w, init=False)
+    x, v, q, step = sysm.get_state()
+    lam, cs = o.derived["lam"], o.derived["cs"]
+    o.set_state(x.T.astype(np.float64) * lam, v.T.astype(np.float64) * cs, q, step)
+    rng = np.random.default_rng(0)
+    m = 64
+    t0 = time.perf_counter()
+    o.accel_subset(rng.choice(w.n_ions, size=m, replace=False))
+    t1 = time.perf_counter() - t0
+    m2 = int(max(64, min(w.n_ions, m * target_s / max(t1, 1e-3))))
+    idx = rng.choice(w.n_ions, size=m2, replace=False)
+    t0 = time.perf_counter()
+    o.accel_subset(idx)
+    dt = time.perf_counter() - t0
+    pairs = m2 * (w.n_ions - 1)
+    pps = pairs / dt
+    return {
+        "value": pps / (w.n_ions - 1),
+        "unit": "ion-steps/s",
+        "cores": O.num_threads(),
+        "kind": "oracle",
+        "sample": f"FP64 ion accelerations (ion-ion + ion-dust + drive) for {m2} random target ions of "
+                  f"the {w.n_ions}-ion state, all ions as sources ({pairs:.3e} pairs in {dt:.1f} s); "
+                  f"ion-steps/s = pairs/s / (N-1); push, charging and reinjection are O(N) and omitted",
+        "pairs_per_s": pps,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n-ions", type=int, default=1 << 20)
+    ap.add_argument("--fp64", action="store_true", help="FP64 state and pair forces")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the design for sharding the ion set across GPUs is described in DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2205_06557_amd import binding as B
+    from paper_2205_06557_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    w = W.two_grain_wake().with_(n_ions=args.n_ions)
+    prec = B.PREC_FP64 if args.fp64 else B.PREC_FP32
+    sysm = B.System(w, precision=prec)
+    N = sysm.N
+    print(f"[bench] {w.name}: N={N} grains={len(w.dust)} precision={'fp64' if prec else 'fp32'}",
+          file=sys.stderr, flush=True)
+    sysm.step(args.warmup)
+    sysm.sync()
+    torch.cuda.synchronize()
+    if torch.distributed.is_available() and torch.distributed.is_initialized():
+        torch.distributed.barrier()
+    sysm.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sysm.step(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sysm.sync()
+    kt = sysm.kernel_times()
+    sysm.set_timing(False)
+    ms_step = 1e3 * wall / args.steps
+    ion_steps = N * args.steps / wall
+    pairs = N * (N - 1) * args.steps / wall
+    pair_ms = kt["pair"][0] / max(kt["pair"][1], 1)
+    push_ms = kt["push"][0] / max(kt["push"][1], 1)
+    fin_ms = kt["finalize"][0] / max(kt["finalize"][1], 1)
+    achieved = FLOP_PER_PAIR * N * (N - 1) / (pair_ms * 1e-3)
+    push_gbs = push_bytes_per_ion(prec) * N / (push_ms * 1e-3)
+    q, _ = sysm.charges()
+    res = {
+        "metric": "ion-steps/s and pair-interactions/s at 2^20 ions",
+        "value": ion_steps,
+        "unit": "ion-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"two-grain wake pair, N={N} ions, 2 grains (r=5um, z=-/+0.25 r_De), "
+                               "Mach 1, nu=0.1 omega_pi, R=3 r_De, H=8 r_De, dt=0.01/omega_pi",
+                   "n_ions": N, "n_dust": len(w.dust), "precision": "fp64" if prec else "fp32"},
+        "pair_interactions_per_s": pairs,
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved / 1e12,
+            "peak": PEAK_FP32 / 1e12,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32,
+            "traffic": None,
+            "kernel": "pair_forces",
+            "flop_per_pair": FLOP_PER_PAIR,
+            "launch_ms": pair_ms,
+        },
+        "push_roofline": {
+            "bound": "hbm",
+            "achieved": push_gbs / 1e9,
+            "peak": PEAK_HBM / 1e9,
+            "unit": "GB/s",
+            "frac": push_gbs / PEAK_HBM,
+            "bytes_per_ion": push_bytes_per_ion(prec),
+            "launch_ms": push_ms,
+        },
+        "kernel_ms": {"pair": pair_ms, "push": push_ms, "finalize": fin_ms},
+        "dust_charge_e": [float(x) / 1.602176634e-19 for x in q],
+    }
+    if not args.no_cpu:
+        print("[bench] timing the CPU oracle on a sample ...", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline(w, sysm, args.cpu_seconds)
+    sysm.close()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,197 @@
+/*
+ * odust.h -- C-ABI of the MI355X dust-in-ion-flow library (libodust.so).
+ *
+ * The library advances the self-consistent model of Kolotinskii & Timofeev,
+ * "OpenDust: A fast GPU-accelerated code for calculation forces, acting on
+ * microparticles in a plasma flow" (arXiv 2205.06557): ion superparticles in
+ * a cylinder (Section 2), electron-screened (Yukawa) ion-ion forces and bare
+ * Coulomb ion-dust forces, a staggered leapfrog push, constant-frequency
+ * charge exchange with neutrals, absorption of ions by fixed dust grains with
+ * the grain charge update, and flux-conserving reinjection of lost ions on
+ * the boundary (Appendix B).  The per-grain observables are the charge and
+ * the four force parts of Eqs. (1)-(4).
+ *
+ * Conventions
+ *  - Inputs follow the paper's parameter objects (Section 3): SI units.
+ *  - Pointers named *host* are host memory owned by the caller; the library
+ *    copies what it needs during the call.  All device memory belongs to the
+ *    library (hipMalloc, or the caller's allocator, see od_allocator).
+ *  - Every call returns od_status.  On failure od_last_error() returns a
+ *    thread-local message.  Kernels report numerical trouble (a NaN in a
+ *    charge or force, a failed initial placement, fixed-point overflow)
+ *    through a device status word; it is read, and returned as OD_ENUMERIC /
+ *    OD_ESTATE, by the next call that synchronises (od_sync, od_get_*).
+ *  - od_step is asynchronous on the system's HIP stream.
+ *  - A system is used by one host thread at a time; distinct systems are
+ *    independent.
+ */
+#ifndef ODUST_H
+#define ODUST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    OD_OK = 0,
+    OD_EINVAL = -1,     /* invalid argument or parameter combination      */
+    OD_EDEVICE = -2,    /* a HIP call failed                              */
+    OD_ENUMERIC = -3,   /* NaN/Inf or overflow detected on the device     */
+    OD_ESTATE = -4,     /* invalid state (e.g. an ion could not be placed) */
+    OD_ENOMEM = -5      /* allocation failed                              */
+} od_status;
+
+/* Charging models of Section 2 ("given", "oml", "consistent"); one model for
+ * all grains (Section 3). */
+typedef enum {
+    OD_CHARGE_GIVEN = 0,
+    OD_CHARGE_OML = 1,
+    OD_CHARGE_CONSISTENT = 2
+} od_charge_mode;
+
+/* od_sim.flags */
+#define OD_FLAG_LITERAL_SIDE 1u  /* side injection with radial + axial velocity only
+                                    (Eqs. B.10-B.11 as printed); default adds the
+                                    tangential thermal component Eq. (B.1) implies */
+#define OD_FLAG_NO_ION_ION 2u    /* test-particle mode: ion-ion force switched off */
+
+/* od_sim.precision */
+#define OD_PREC_FP32 0           /* FP32 state and pair tiles, FP64 charge/force sums */
+#define OD_PREC_FP64 1           /* FP64 state and pair forces throughout              */
+
+#define OD_MAX_DUST 32
+
+/* Plasma parameters (Section 3, plasma parameter classes), SI. */
+typedef struct {
+    double T_e;      /* electron temperature, K                                    */
+    double T_i;      /* ion (and neutral) temperature, K                           */
+    double n_inf;    /* ion density of the quasi-neutral plasma, m^-3               */
+    double m_i;      /* ion mass, kg                                               */
+    double mach;     /* flow speed along +z in units of sqrt(kB T_e / m_i)          */
+    double nu_in;    /* ion-neutral charge-exchange frequency, s^-1 (0: collisionless) */
+    double E_ext;    /* driving field along +z, V/m; NaN: m_i nu_in u / e           */
+} od_plasma;
+
+/* Simulation parameters (Section 3, simulation parameter class), SI. */
+typedef struct {
+    double R;            /* cylinder radius, m                              */
+    double H;            /* cylinder height, m (axis from -H/2 to +H/2)      */
+    double dt;           /* time step, s                                    */
+    int64_t n_ions;      /* number of ion superparticles N (>= 2)            */
+    int64_t n_discard;   /* steps excluded from the time averages           */
+    uint64_t seed;       /* random stream key, word 0                       */
+    uint64_t system_id;  /* random stream key, word 1                       */
+    int32_t charge_mode; /* od_charge_mode                                  */
+    int32_t precision;   /* OD_PREC_FP32 or OD_PREC_FP64                    */
+    uint32_t flags;      /* OD_FLAG_*                                       */
+    uint32_t reserved;   /* must be 0                                       */
+} od_sim;
+
+/* One dust grain (Section 3, dust particle class): fixed position, radius,
+ * initial charge. */
+typedef struct {
+    double x, y, z;      /* m                                               */
+    double radius;       /* m                                               */
+    double q0;           /* initial charge, C                               */
+} od_dust;
+
+/* Optional device allocator (e.g. a framework's caching allocator).  alloc
+ * returns device memory of at least `bytes` bytes, 256-byte aligned, or
+ * NULL; release gives it back.  Both are called only from od_init_system and
+ * od_destroy. */
+typedef struct {
+    void* (*alloc)(void* ctx, size_t bytes);
+    void (*release)(void* ctx, void* ptr);
+    void* ctx;
+} od_allocator;
+
+typedef struct od_system od_system;
+
+/* Creates a system and draws its initial state on the device: positions
+ * uniform in the cylinder outside every grain, velocities from the shifted
+ * Maxwellian N((0,0,u), kB T_i/m_i), charges q0 (Section 2).
+ *   dust:      n_dust grains, host, 0 <= n_dust <= OD_MAX_DUST;
+ *   hip_stream: hipStream_t to run on (NULL: the default stream);
+ *   allocator: NULL for hipMalloc/hipFree.
+ * Errors: OD_EINVAL (N < 2, non-positive sizes or temperatures, a grain that
+ * crosses the wall or overlaps another, bad mode/precision/flags),
+ * OD_ENOMEM, OD_EDEVICE, OD_ESTATE (an ion could not be placed). */
+od_status od_init_system(const od_plasma* plasma, const od_sim* sim, const od_dust* dust,
+                         int32_t n_dust, void* hip_stream, const od_allocator* allocator,
+                         od_system** out);
+
+/* Advances n_steps >= 0 time steps (Section 2 and Appendix B): forces at the
+ * current positions and charges, kick, charge exchange, drift, absorption,
+ * exit, charge update, collection force (Eq. 3), reinjection, recording.
+ * Asynchronous; returns after the launches are queued. */
+od_status od_step(od_system* sys, int64_t n_steps);
+
+/* Waits for the system's stream and returns the device status. */
+od_status od_sync(od_system* sys);
+
+/* Dust charges, C: q_now[n_dust] after the last step; q_avg[n_dust] (may be
+ * NULL) the mean of the recorded charges over steps >= n_discard. */
+od_status od_get_dust_charges(od_system* sys, double* q_now_host, double* q_avg_host);
+
+/* Dust forces, N, f_host[n_dust][4][3]: parts orbit (Eq. 1), dust-dust
+ * (Eq. 2), collection (Eq. 3), external field (Eq. 4).
+ *   which = 0: the forces recorded at the last step;
+ *   which = 1: their means over steps >= n_discard. */
+od_status od_get_dust_forces(od_system* sys, int32_t which, double* f_host);
+
+/* Frees the system's device memory. NULL is ignored. */
+void od_destroy(od_system* sys);
+
+/* Thread-local text of the last error. */
+const char* od_last_error(void);
+
+/* ---- inspection and test surface --------------------------------------- */
+
+/* Units of the dimensionless state: units_host[4] = {length r_De (m),
+ * time 1/omega_pi (s), velocity c_s = r_De omega_pi (m/s),
+ * acceleration r_De omega_pi^2 (m/s^2)}. */
+od_status od_get_units(od_system* sys, double* units_host);
+
+/* Sizes: out_host[4] = {N, n_dust, precision, padded N}. */
+od_status od_get_sizes(od_system* sys, int64_t* out_host);
+
+/* State in dimensionless units, structure of arrays: x_host[3][N] and
+ * v_host[3][N] (v is the half-step velocity), float for OD_PREC_FP32 and
+ * double for OD_PREC_FP64; q_host[n_dust] in C; *step the step counter.
+ * Any pointer may be NULL. */
+od_status od_get_state(od_system* sys, void* x_host, void* v_host, double* q_host, int64_t* step);
+
+/* Replaces the state (same layouts; NULL leaves a part unchanged). Ions
+ * inside a grain give OD_ESTATE, non-finite values OD_ENUMERIC. */
+od_status od_set_state(od_system* sys, const void* x_host, const void* v_host, const double* q_host,
+                       int64_t step);
+
+/* Accelerations of the last step's force evaluation, dimensionless, [3][N]
+ * (float or double as the state). */
+od_status od_get_accelerations(od_system* sys, void* a_host);
+
+/* Events of the last step: ev_host[N] bytes (0 none, 1 exited, 2 + d
+ * absorbed by grain d; bit 7 set if a charge-exchange collision happened),
+ * n_abs_host[n_dust] absorbed counts, *n_exit, *n_coll.  Any may be NULL. */
+od_status od_get_step_events(od_system* sys, uint8_t* ev_host, int64_t* n_abs_host,
+                             int64_t* n_exit, int64_t* n_coll);
+
+/* One Philox4x64-10 block computed on the device: out_host[4] for counter
+ * ctr_host[4] and key (seed, system). */
+od_status od_rng_block(uint64_t seed, uint64_t system, const uint64_t* ctr_host, uint64_t* out_host);
+
+/* Kernel timing with HIP events on the system's stream.  While enabled,
+ * od_step brackets every launch; od_get_kernel_times synchronises and
+ * returns, per kernel class {0 pair forces, 1 push, 2 finalize}, the summed
+ * milliseconds ms_host[3] and launch counts launches_host[3] since enabling,
+ * then resets them. */
+od_status od_set_timing(od_system* sys, int32_t enable);
+od_status od_get_kernel_times(od_system* sys, double* ms_host, int64_t* launches_host);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ODUST_H */

@@ -1,0 +1,246 @@
+"""ctypes binding of libodust.so (the C-ABI of include/odust.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  PyTorch, when present, supplies the HIP stream and (optionally) the
+device memory through the library's allocator hook.  If the library has not
+been built this module raises; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libodust.so")
+
+OD_OK, OD_EINVAL, OD_EDEVICE, OD_ENUMERIC, OD_ESTATE, OD_ENOMEM = 0, -1, -2, -3, -4, -5
+PREC_FP32, PREC_FP64 = 0, 1
+EV_NONE, EV_EXIT, EV_ABS_BASE, EV_COLL_BIT = 0, 1, 2, 0x80
+KERNEL_CLASSES = ("pair", "push", "finalize")
+
+
+class OdError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"odust error {status}: {msg}")
+        self.status = status
+
+
+class Plasma(C.Structure):
+    _fields_ = [("T_e", C.c_double), ("T_i", C.c_double), ("n_inf", C.c_double),
+                ("m_i", C.c_double), ("mach", C.c_double), ("nu_in", C.c_double),
+                ("E_ext", C.c_double)]
+
+
+class Sim(C.Structure):
+    _fields_ = [("R", C.c_double), ("H", C.c_double), ("dt", C.c_double),
+                ("n_ions", C.c_int64), ("n_discard", C.c_int64), ("seed", C.c_uint64),
+                ("system_id", C.c_uint64), ("charge_mode", C.c_int32), ("precision", C.c_int32),
+                ("flags", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class Dust(C.Structure):
+    _fields_ = [("x", C.c_double), ("y", C.c_double), ("z", C.c_double),
+                ("radius", C.c_double), ("q0", C.c_double)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("release", FREE_FN), ("ctx", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libodust.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2205_06557_amd.build` (no CPU fallback exists)")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, u64 = C.c_void_p, C.c_int64, C.c_uint64
+        L.od_init_system.argtypes = [C.POINTER(Plasma), C.POINTER(Sim), C.POINTER(Dust), C.c_int32,
+                                     vp, C.POINTER(Allocator), C.POINTER(vp)]
+        L.od_step.argtypes = [vp, i64]
+        L.od_sync.argtypes = [vp]
+        L.od_get_dust_charges.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.od_get_dust_forces.argtypes = [vp, C.c_int32, C.POINTER(C.c_double)]
+        L.od_destroy.argtypes = [vp]
+        L.od_destroy.restype = None
+        L.od_last_error.restype = C.c_char_p
+        L.od_get_units.argtypes = [vp, C.POINTER(C.c_double)]
+        L.od_get_sizes.argtypes = [vp, C.POINTER(C.c_int64)]
+        L.od_get_state.argtypes = [vp, vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.od_set_state.argtypes = [vp, vp, vp, C.POINTER(C.c_double), i64]
+        L.od_get_accelerations.argtypes = [vp, vp]
+        L.od_get_step_events.argtypes = [vp, C.POINTER(C.c_uint8), C.POINTER(C.c_int64),
+                                         C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.od_rng_block.argtypes = [u64, u64, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
+        L.od_set_timing.argtypes = [vp, C.c_int32]
+        L.od_get_kernel_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        for name in ("od_init_system", "od_step", "od_sync", "od_get_dust_charges",
+                     "od_get_dust_forces", "od_get_units", "od_get_sizes", "od_get_state",
+                     "od_set_state", "od_get_accelerations", "od_get_step_events",
+                     "od_rng_block", "od_set_timing", "od_get_kernel_times"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(st: int):
+    if st != OD_OK:
+        raise OdError(st, lib().od_last_error().decode(errors="replace"))
+
+
+def _ptr(a: Optional[np.ndarray], ctype=C.c_double):
+    return None if a is None else a.ctypes.data_as(C.POINTER(ctype))
+
+
+def _torch_stream():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+    except Exception:
+        pass
+    return None
+
+
+class TorchAllocator:
+    """Device memory from PyTorch's caching allocator, handed to the library
+    through its allocator hook."""
+
+    def __init__(self):
+        import torch
+        self._torch = torch
+        self._live = {}
+
+        def _alloc(ctx, nbytes):
+            t = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device="cuda")
+            p = (t.data_ptr() + 255) // 256 * 256
+            self._live[p] = t
+            return p
+
+        def _free(ctx, ptr):
+            self._live.pop(ptr, None)
+
+        self._a = ALLOC_FN(_alloc)
+        self._f = FREE_FN(_free)
+        self.struct = Allocator(self._a, self._f, None)
+
+
+def rng_block(seed: int, system: int, ctr) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint64)
+    out = np.zeros(4, dtype=np.uint64)
+    _check(lib().od_rng_block(seed, system, _ptr(c, C.c_uint64), _ptr(out, C.c_uint64)))
+    return out
+
+
+class System:
+    """One dust system on the GPU.  `w` is a workloads.Workload (SI)."""
+
+    def __init__(self, w, precision: int = PREC_FP32, stream=None, torch_memory: bool = False,
+                 n_ions: Optional[int] = None):
+        L = lib()
+        self.w = w
+        pl = Plasma(w.Te, w.Ti, w.n_inf, w.m_i, w.mach, w.nu_in, w.E_ext)
+        N = int(n_ions if n_ions is not None else w.n_ions)
+        sim = Sim(w.R, w.H, w.dt, N, int(w.n_discard), int(w.seed), int(w.system_id),
+                  int(w.charge_mode), int(precision), int(w.flags), 0)
+        nd = len(w.dust)
+        dust = (Dust * max(nd, 1))(*[Dust(*d) for d in w.dust])
+        if stream is None:
+            stream = _torch_stream()
+        self._alloc = TorchAllocator() if torch_memory else None
+        h = C.c_void_p()
+        _check(L.od_init_system(C.byref(pl), C.byref(sim), dust, nd, stream,
+                                C.byref(self._alloc.struct) if self._alloc else None, C.byref(h)))
+        self._h = h
+        sz = np.zeros(4, dtype=np.int64)
+        _check(L.od_get_sizes(h, _ptr(sz, C.c_int64)))
+        self.N, self.nd, self.precision, self.Npad = (int(x) for x in sz)
+        self.dtype = np.float32 if self.precision == PREC_FP32 else np.float64
+        u = np.zeros(4)
+        _check(L.od_get_units(h, _ptr(u)))
+        self.units = dict(length=u[0], time=u[1], velocity=u[2], accel=u[3])
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().od_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # --- stepping ---------------------------------------------------------
+    def step(self, n: int = 1):
+        _check(lib().od_step(self._h, int(n)))
+
+    def sync(self):
+        _check(lib().od_sync(self._h))
+
+    # --- observables --------------------------------------------------------
+    def charges(self):
+        q = np.zeros(max(self.nd, 1))
+        qa = np.zeros(max(self.nd, 1))
+        _check(lib().od_get_dust_charges(self._h, _ptr(q), _ptr(qa)))
+        return q[: self.nd], qa[: self.nd]
+
+    def forces(self, which: int = 0) -> np.ndarray:
+        f = np.zeros((max(self.nd, 1), 4, 3))
+        _check(lib().od_get_dust_forces(self._h, which, _ptr(f)))
+        return f[: self.nd]
+
+    # --- state --------------------------------------------------------------
+    def get_state(self):
+        x = np.zeros((3, self.N), dtype=self.dtype)
+        v = np.zeros((3, self.N), dtype=self.dtype)
+        q = np.zeros(max(self.nd, 1))
+        st = C.c_int64(0)
+        _check(lib().od_get_state(self._h, x.ctypes.data, v.ctypes.data, _ptr(q), C.byref(st)))
+        return x, v, q[: self.nd], st.value
+
+    def set_state(self, x=None, v=None, q=None, step: int = 0):
+        xs = None if x is None else np.ascontiguousarray(x, dtype=self.dtype).reshape(3, self.N)
+        vs = None if v is None else np.ascontiguousarray(v, dtype=self.dtype).reshape(3, self.N)
+        qs = None if q is None else np.ascontiguousarray(q, dtype=np.float64)
+        _check(lib().od_set_state(self._h, None if xs is None else xs.ctypes.data,
+                                  None if vs is None else vs.ctypes.data, _ptr(qs), int(step)))
+
+    def accelerations(self) -> np.ndarray:
+        a = np.zeros((3, self.N), dtype=self.dtype)
+        _check(lib().od_get_accelerations(self._h, a.ctypes.data))
+        return a
+
+    def events(self):
+        ev = np.zeros(self.N, dtype=np.uint8)
+        nabs = np.zeros(max(self.nd, 1), dtype=np.int64)
+        ne = C.c_int64(0)
+        nc = C.c_int64(0)
+        _check(lib().od_get_step_events(self._h, _ptr(ev, C.c_uint8), _ptr(nabs, C.c_int64),
+                                        C.byref(ne), C.byref(nc)))
+        return ev, nabs[: self.nd], ne.value, nc.value
+
+    # --- timing -------------------------------------------------------------
+    def set_timing(self, enable: bool):
+        _check(lib().od_set_timing(self._h, 1 if enable else 0))
+
+    def kernel_times(self):
+        ms = np.zeros(3)
+        n = np.zeros(3, dtype=np.int64)
+        _check(lib().od_get_kernel_times(self._h, _ptr(ms), _ptr(n, C.c_int64)))
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_CLASSES)}

@@ -1,0 +1,130 @@
+// device_common.hpp -- shared device helpers of libodust: the counter-based
+// generator, uniform and normal draws, fixed-point accumulation and wave
+// reductions.  Units inside the kernels are dimensionless: lengths in the
+// electron Debye length r_De, times in 1/omega_pi, velocities in
+// c_s = r_De omega_pi, charges in e.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace odk {
+
+constexpr int kMaxDust = 32;
+constexpr double kPi = 3.14159265358979323846;
+
+// Random-stream purposes (third counter word).
+enum : uint64_t { kInitPos = 0, kInitVel = 1, kColl = 2, kReinj = 3 };
+
+// Per-ion event byte.
+enum : uint8_t { kEvNone = 0, kEvExit = 1, kEvAbsBase = 2, kEvCollBit = 0x80 };
+
+// Device status bits.
+enum : int { kStNaN = 1, kStPlace = 2, kStOverflow = 4 };
+
+// Fixed-point scales of the integer accumulators (two's-complement int64
+// sums are associative, so the totals do not depend on the order in which
+// blocks add them).
+constexpr double kForceScale = 4294967296.0;    // 2^32: Eq. (1) sums, dimensionless
+constexpr double kMomScale = 4294967296.0;      // 2^32: absorbed velocity sums, c_s
+
+// Layout of one system's control block (device memory, int64/double words).
+struct Ctl {
+    unsigned long long acc[kMaxDust][8];   // [0..2] Eq.(1) sum, [3] absorbed count, [4..6] sum v
+    unsigned long long cnt[4];             // [0] exits, [1] collisions
+    double Q[kMaxDust];                    // charge, e
+    double last[kMaxDust][16];             // [0] Q^n, [1..12] F parts (SI), [13] absorbed count
+    double sums[kMaxDust][16];             // running sums over recorded steps
+    long long step;                        // step counter n
+    long long nrec;                        // recorded steps
+    long long last_exit, last_coll;
+    int status;
+    int pad[7];
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x64 with 10 rounds (Salmon et al., SC'11): per round two 64x64->128
+// products; the words are permuted and the high halves mixed with the key;
+// the key advances by two Weyl increments between rounds.
+struct U64x4 {
+    uint64_t w[4];
+};
+
+__host__ __device__ inline void mul128(uint64_t a, uint64_t b, uint64_t& hi, uint64_t& lo)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    lo = a * b;
+    hi = __umul64hi(a, b);
+#else
+    unsigned __int128 p = (unsigned __int128)a * b;
+    lo = (uint64_t)p;
+    hi = (uint64_t)(p >> 64);
+#endif
+}
+
+__host__ __device__ inline U64x4 philox(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                        uint64_t k0, uint64_t k1)
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint64_t h0, l0, h1, l1;
+        mul128(M0, c0, h0, l0);
+        mul128(M1, c2, h1, l1);
+        const uint64_t t0 = h1 ^ c1 ^ k0;
+        const uint64_t t2 = h0 ^ c3 ^ k1;
+        c0 = t0;
+        c1 = l1;
+        c2 = t2;
+        c3 = l0;
+        k0 += W0;
+        k1 += W1;
+    }
+    U64x4 o;
+    o.w[0] = c0; o.w[1] = c1; o.w[2] = c2; o.w[3] = c3;
+    return o;
+}
+
+// Uniform strictly inside (0,1): 52 high bits plus one half, over 2^52.
+__host__ __device__ inline double unit(uint64_t w)
+{
+    return ((double)(w >> 12) + 0.5) * 2.220446049250313080847e-16;
+}
+
+// Box-Muller: two standard normals from two uniforms.
+__device__ inline void gauss2(double ua, double ub, double& g1, double& g2)
+{
+    const double m = sqrt(-2.0 * log(ua));
+    double s, c;
+    sincos(2.0 * kPi * ub, &s, &c);
+    g1 = m * c;
+    g2 = m * s;
+}
+
+// ---------------------------------------------------------------------------
+// Wave64 reduction of a double (butterfly over xor masks).
+__device__ inline double wave_sum(double v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+__device__ inline unsigned long long to_fixed(double v, double scale, int* status)
+{
+    double s = v * scale;
+    const double lim = 4.0e18;
+    if (!(s < lim && s > -lim)) {   // also catches NaN
+        atomicOr(status, (s != s) ? kStNaN : kStOverflow);
+        s = 0.0;
+    }
+    return (unsigned long long)__double2ll_rn(s);
+}
+
+__host__ __device__ inline double from_fixed(unsigned long long v, double scale)
+{
+    return (double)(long long)v / scale;
+}
+
+}  // namespace odk

@@ -1,0 +1,539 @@
+// kernels.hpp -- the HIP kernels of one time step.
+//
+//   pair_forces_f32 / pair_forces_f64   forces on every ion (Section 2):
+//       screened (Yukawa) ion-ion sum over all other ions, bare Coulomb pull
+//       of each grain, homogeneous drive; plus the per-grain sum of Eq. (1)
+//       over all ions, reduced per block and added to int64 fixed-point
+//       accumulators.
+//   push_kernel<T>      kick, charge exchange, drift, absorption test against
+//       every grain along the drift segment, exit test, reinjection on the
+//       boundary (Appendix B), per-ion event byte.
+//   finalize_kernel     one wave: charge update (the three charging models of
+//       Section 2), the four force parts of Eqs. (1)-(4) in SI, recording,
+//       time averages, clearing of the accumulators, step counter.
+//   init_kernel<T>      initial uniform positions and shifted-Maxwellian
+//       velocities.
+//
+// Dimensionless units: length r_De, time 1/omega_pi, velocity c_s, charge e.
+#pragma once
+
+#include "device_common.hpp"
+
+namespace odk {
+
+struct DustSet {
+    int nd;
+    int pad_;
+    double pos[kMaxDust][3];
+    double rad2[kMaxDust];
+};
+
+struct PairArgs {
+    int N, Npad, nd, ion_ion;
+    float C;        // ion-ion coupling: (superparticle weight)/(4 pi n r_De^3) = V/(4 pi N)
+    float pad_;
+    double Cd;      // same in FP64
+    double Kq;      // ion<-grain coupling per unit grain charge (e): 1/(4 pi n r_De^3)
+    double Ez;      // homogeneous drive along z (dimensionless acceleration)
+};
+
+struct PushArgs {
+    int N, Npad, nd;
+    unsigned flags;
+    double dt, sig, ubar, R, H;
+    uint64_t k0, k1, Tc, Tb, Tbt;
+};
+
+struct FinalArgs {
+    int nd, mode;
+    long long n_discard;
+    double dt;                      // dimensionless step
+    double w;                       // superparticle weight (ions per superparticle)
+    double Ie0[kMaxDust];           // electron random current at phi = 0, e per unit time
+    double Ii0[kMaxDust];           // ion thermal current factor pi a^2 n v_t, e per unit time
+    double psi[kMaxDust];           // e phi / kB Te per unit charge (e)
+    double s_oml, te_over_ti;       // drift / v_t ; Te/Ti
+    double c_orbit;                 // N per (e * dimensionless Eq.(1) sum), times w
+    double c_dd;                    // N per e^2 per dimensionless 1/r^2
+    double c_coll;                  // N per (dimensionless velocity sum)
+    double c_ext;                   // N per e (e * E_SI)
+};
+
+// ---------------------------------------------------------------------------
+// Forces, FP32 tiles.  One ion per thread; the block stages TJ source ions at
+// a time in LDS as float4 and every lane reads them with a broadcast load.
+// Inner sums run in FP32 over one tile and are added to FP64 totals per tile.
+template <int BLOCK, int TJ>
+__global__ __launch_bounds__(BLOCK) void pair_forces_f32(const float* __restrict__ xs,
+                                                         float* __restrict__ acc,
+                                                         PairArgs p, DustSet ds,
+                                                         Ctl* __restrict__ ctl)
+{
+    __shared__ float4 tile[TJ];
+    __shared__ double red[BLOCK / 64][kMaxDust][3];
+    const int Npad = p.Npad;
+    const float* X = xs;
+    const float* Y = xs + Npad;
+    const float* Z = xs + 2 * Npad;
+    const int i0 = blockIdx.x * BLOCK;
+    const int i = i0 + threadIdx.x;
+    const float xi = X[i], yi = Y[i], zi = Z[i];
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    const float kNegLog2e = -1.4426950408889634f;
+
+    if (p.ion_ion) {
+        for (int j0 = 0; j0 < Npad; j0 += TJ) {
+            __syncthreads();
+            for (int t = threadIdx.x; t < TJ; t += BLOCK)
+                tile[t] = make_float4(X[j0 + t], Y[j0 + t], Z[j0 + t], 0.0f);
+            __syncthreads();
+            float ax = 0.0f, ay = 0.0f, az = 0.0f;
+            const bool diag = (j0 < i0 + BLOCK) && (i0 < j0 + TJ);
+            if (!diag) {
+#pragma unroll 8
+                for (int k = 0; k < TJ; ++k) {
+                    const float4 q = tile[k];
+                    const float dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
+                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                    const float ri = __builtin_amdgcn_rsqf(r2);
+                    const float r = r2 * ri;
+                    const float e = __builtin_amdgcn_exp2f(r * kNegLog2e);
+                    const float ri2 = ri * ri;
+                    const float f = fmaf(ri2, ri, ri2) * e;      // (1 + r) e^-r / r^3
+                    ax = fmaf(f, dx, ax);
+                    ay = fmaf(f, dy, ay);
+                    az = fmaf(f, dz, az);
+                }
+            } else {
+                const int kself = i - j0;
+                for (int k = 0; k < TJ; ++k) {
+                    const float4 q = tile[k];
+                    const float dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
+                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                    const float ri = __builtin_amdgcn_rsqf(r2);
+                    const float r = r2 * ri;
+                    const float e = __builtin_amdgcn_exp2f(r * kNegLog2e);
+                    const float ri2 = ri * ri;
+                    float f = fmaf(ri2, ri, ri2) * e;
+                    f = (k == kself) ? 0.0f : f;
+                    ax = fmaf(f, dx, ax);
+                    ay = fmaf(f, dy, ay);
+                    az = fmaf(f, dz, az);
+                }
+            }
+            sx += (double)ax;
+            sy += (double)ay;
+            sz += (double)az;
+        }
+    }
+
+    // Epilogue: grain terms in FP64 (N_d per ion).
+    const bool live = i < p.N;
+    const double xd = xi, yd = yi, zd = zi;
+    double gx = p.Cd * sx, gy = p.Cd * sy, gz = p.Cd * sz + p.Ez;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int d = 0; d < ds.nd; ++d) {
+        const double rx = xd - ds.pos[d][0], ry = yd - ds.pos[d][1], rz = zd - ds.pos[d][2];
+        const double r2 = rx * rx + ry * ry + rz * rz;
+        const double r = sqrt(r2);
+        const double ir3 = 1.0 / (r2 * r);
+        const double kq = p.Kq * ctl->Q[d] * ir3;               // bare Coulomb on the ion
+        gx += kq * rx; gy += kq * ry; gz += kq * rz;
+        // Eq. (1) summand: (1 + rho) e^-rho / rho^3 (r_d - x_i)
+        double f = live ? -(1.0 + r) * exp(-r) * ir3 : 0.0;
+        double fx = wave_sum(f * rx), fy = wave_sum(f * ry), fz = wave_sum(f * rz);
+        if (lane == 0) {
+            red[wv][d][0] = fx;
+            red[wv][d][1] = fy;
+            red[wv][d][2] = fz;
+        }
+    }
+    if (live) {
+        acc[i] = (float)gx;
+        acc[Npad + i] = (float)gy;
+        acc[2 * Npad + i] = (float)gz;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < ds.nd * 3; t += BLOCK) {
+        const int d = t / 3, c = t % 3;
+        double s = 0.0;
+        for (int w = 0; w < BLOCK / 64; ++w) s += red[w][d][c];
+        atomicAdd(&ctl->acc[d][c], to_fixed(s, kForceScale, &ctl->status));
+    }
+}
+
+// Forces, FP64 throughout (precision mode OD_PREC_FP64).
+template <int BLOCK, int TJ>
+__global__ __launch_bounds__(BLOCK) void pair_forces_f64(const double* __restrict__ xs,
+                                                         double* __restrict__ acc,
+                                                         PairArgs p, DustSet ds,
+                                                         Ctl* __restrict__ ctl)
+{
+    __shared__ double4 tile[TJ];
+    __shared__ double red[BLOCK / 64][kMaxDust][3];
+    const int Npad = p.Npad;
+    const double* X = xs;
+    const double* Y = xs + Npad;
+    const double* Z = xs + 2 * Npad;
+    const int i0 = blockIdx.x * BLOCK;
+    const int i = i0 + threadIdx.x;
+    const double xi = X[i], yi = Y[i], zi = Z[i];
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    if (p.ion_ion) {
+        for (int j0 = 0; j0 < Npad; j0 += TJ) {
+            __syncthreads();
+            for (int t = threadIdx.x; t < TJ; t += BLOCK) {
+                double4 q;
+                q.x = X[j0 + t]; q.y = Y[j0 + t]; q.z = Z[j0 + t]; q.w = 0.0;
+                tile[t] = q;
+            }
+            __syncthreads();
+            for (int k = 0; k < TJ; ++k) {
+                const double4 q = tile[k];
+                const double dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                const double r = sqrt(r2);
+                double f = (1.0 + r) * exp(-r) / (r2 * r);
+                f = (j0 + k == i) ? 0.0 : f;
+                sx += f * dx;
+                sy += f * dy;
+                sz += f * dz;
+            }
+        }
+    }
+    const bool live = i < p.N;
+    double gx = p.Cd * sx, gy = p.Cd * sy, gz = p.Cd * sz + p.Ez;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int d = 0; d < ds.nd; ++d) {
+        const double rx = xi - ds.pos[d][0], ry = yi - ds.pos[d][1], rz = zi - ds.pos[d][2];
+        const double r2 = rx * rx + ry * ry + rz * rz;
+        const double r = sqrt(r2);
+        const double ir3 = 1.0 / (r2 * r);
+        const double kq = p.Kq * ctl->Q[d] * ir3;
+        gx += kq * rx; gy += kq * ry; gz += kq * rz;
+        double f = live ? -(1.0 + r) * exp(-r) * ir3 : 0.0;
+        double fx = wave_sum(f * rx), fy = wave_sum(f * ry), fz = wave_sum(f * rz);
+        if (lane == 0) {
+            red[wv][d][0] = fx;
+            red[wv][d][1] = fy;
+            red[wv][d][2] = fz;
+        }
+    }
+    if (live) {
+        acc[i] = gx;
+        acc[Npad + i] = gy;
+        acc[2 * Npad + i] = gz;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < ds.nd * 3; t += BLOCK) {
+        const int d = t / 3, c = t % 3;
+        double s = 0.0;
+        for (int w = 0; w < BLOCK / 64; ++w) s += red[w][d][c];
+        atomicAdd(&ctl->acc[d][c], to_fixed(s, kForceScale, &ctl->status));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Boundary sampling helpers (Appendix B), dimensionless, FP64.
+
+__device__ inline double npdf(double t) { return 0.3989422804014326779 * exp(-0.5 * t * t); }
+
+// Inflow per unit area through a face whose inward normal velocity is
+// N(m, s^2): int_0^inf v phi(v) dv.
+__device__ inline double inflow(double m, double s)
+{
+    return m * 0.5 * erfc(-m / (s * 1.4142135623730950488)) + s * npdf(m / s);
+}
+
+// Flux-weighted normal speed on a face: the v >= 0 whose flux tail
+// int_v^inf v' phi(v') dv' equals uu times the total inflow.  Newton on the
+// tail (slope -v phi(v)) inside a shrinking bracket, bisection when a Newton
+// step leaves it; stops when a step is below 1e-13 s.
+__device__ double flux_speed(double uu, double m, double s)
+{
+    const double goal = uu * inflow(m, s);
+    double lo = 0.0;
+    double hi = fmax(m, 0.0) + 40.0 * s;
+    double v = fmax(m, 0.0) + s;
+    for (int it = 0; it < 400; ++it) {
+        const double t = (v - m) / s;
+        const double tail = m * 0.5 * erfc(t * 0.70710678118654752440) + s * npdf(t);
+        const double g = tail - goal;
+        if (g > 0.0) lo = v; else hi = v;
+        const double slope = -v * npdf(t) / s;
+        double nv = 0.5 * (lo + hi);
+        if (slope < 0.0) {
+            const double cand = v - g / slope;
+            if (cand > lo && cand < hi) nv = cand;
+        }
+        const bool done = fabs(nv - v) <= 1e-13 * s;
+        v = nv;
+        if (done) break;
+    }
+    return v;
+}
+
+// New position and velocity of a lost ion, from blocks (i, n, REINJ, 0/1).
+__device__ void reinject(const PushArgs& p, uint64_t ion, uint64_t n, double o[6])
+{
+    const U64x4 a = philox(ion, n, kReinj, 0, p.k0, p.k1);
+    const U64x4 b = philox(ion, n, kReinj, 1, p.k0, p.k1);
+    double g1, g2;
+    gauss2(unit(b.w[0]), unit(b.w[1]), g1, g2);
+    if (a.w[0] < p.Tbt) {                       // bottom or top disk
+        const bool bottom = a.w[0] < p.Tb;
+        const double rr = p.R * sqrt(unit(a.w[1]));
+        double sn, cs;
+        sincos(2.0 * kPi * unit(a.w[2]), &sn, &cs);
+        o[0] = rr * cs;
+        o[1] = rr * sn;
+        o[2] = bottom ? -0.5 * p.H : 0.5 * p.H;
+        o[3] = p.sig * g1;
+        o[4] = p.sig * g2;
+        o[5] = bottom ? flux_speed(unit(a.w[3]), p.ubar, p.sig)
+                      : -flux_speed(unit(a.w[3]), -p.ubar, p.sig);
+    } else {                                    // side wall
+        double sn, cs;
+        sincos(2.0 * kPi * unit(a.w[1]), &sn, &cs);
+        o[0] = p.R * cs;
+        o[1] = p.R * sn;
+        o[2] = p.H * (unit(a.w[2]) - 0.5);
+        const double vr = p.sig * sqrt(-2.0 * log(unit(a.w[3])));
+        const double vt = (p.flags & 1u) ? 0.0 : p.sig * g2;
+        o[3] = -vr * cs - vt * sn;
+        o[4] = -vr * sn + vt * cs;
+        o[5] = p.ubar + p.sig * g1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Push: one ion per thread.
+template <typename T>
+__global__ __launch_bounds__(256) void push_kernel(T* __restrict__ xs, T* __restrict__ vs,
+                                                   const T* __restrict__ as,
+                                                   uint8_t* __restrict__ ev, PushArgs p,
+                                                   DustSet ds, Ctl* __restrict__ ctl)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int Npad = p.Npad;
+    const uint64_t n = (uint64_t)ctl->step;
+    bool coll = false;
+    uint8_t code = kEvNone;
+    if (i < p.N) {
+        const T dt = (T)p.dt;
+        T x0 = xs[i], x1 = xs[Npad + i], x2 = xs[2 * Npad + i];
+        T v0 = vs[i] + dt * as[i];
+        T v1 = vs[Npad + i] + dt * as[Npad + i];
+        T v2 = vs[2 * Npad + i] + dt * as[2 * Npad + i];
+        if (p.Tc != 0) {
+            const U64x4 r = philox((uint64_t)i, n, kColl, 0, p.k0, p.k1);
+            if (r.w[0] < p.Tc) {
+                const U64x4 g = philox((uint64_t)i, n, kColl, 1, p.k0, p.k1);
+                double g1, g2, g3, g4;
+                gauss2(unit(g.w[0]), unit(g.w[1]), g1, g2);
+                gauss2(unit(g.w[2]), unit(g.w[3]), g3, g4);
+                v0 = (T)(p.sig * g1);
+                v1 = (T)(p.sig * g2);
+                v2 = (T)(p.sig * g3);
+                coll = true;
+            }
+        }
+        const T y0 = x0 + dt * v0, y1 = x1 + dt * v1, y2 = x2 + dt * v2;
+        // Absorption: does the drift segment x -> y meet a grain?  FP64 on
+        // the stored values; the earliest entry wins, ties to the lower index.
+        int hit = -1;
+        double tbest = 2.0;
+        const double D0 = (double)y0 - (double)x0, D1 = (double)y1 - (double)x1,
+                     D2 = (double)y2 - (double)x2;
+        const double DD = D0 * D0 + D1 * D1 + D2 * D2;
+        for (int d = 0; d < ds.nd; ++d) {
+            const double s0 = (double)x0 - ds.pos[d][0], s1 = (double)x1 - ds.pos[d][1],
+                         s2 = (double)x2 - ds.pos[d][2];
+            const double ss = s0 * s0 + s1 * s1 + s2 * s2;
+            const double sD = s0 * D0 + s1 * D1 + s2 * D2;
+            double th;
+            bool in;
+            if (DD > 0.0) {
+                const double tc = fmin(fmax(-sD / DD, 0.0), 1.0);
+                const double c0 = s0 + tc * D0, c1 = s1 + tc * D1, c2 = s2 + tc * D2;
+                in = c0 * c0 + c1 * c1 + c2 * c2 <= ds.rad2[d];
+                const double disc = fmax(sD * sD - DD * (ss - ds.rad2[d]), 0.0);
+                th = fmax((-sD - sqrt(disc)) / DD, 0.0);
+            } else {
+                in = ss <= ds.rad2[d];
+                th = 0.0;
+            }
+            if (in && th < tbest) {
+                tbest = th;
+                hit = d;
+            }
+        }
+        bool lost = false;
+        if (hit >= 0) {
+            code = (uint8_t)(kEvAbsBase + hit);
+            atomicAdd(&ctl->acc[hit][3], 1ull);
+            atomicAdd(&ctl->acc[hit][4], to_fixed((double)v0, kMomScale, &ctl->status));
+            atomicAdd(&ctl->acc[hit][5], to_fixed((double)v1, kMomScale, &ctl->status));
+            atomicAdd(&ctl->acc[hit][6], to_fixed((double)v2, kMomScale, &ctl->status));
+            lost = true;
+        } else {
+            const double rr = (double)y0 * (double)y0 + (double)y1 * (double)y1;
+            if (rr > p.R * p.R || fabs((double)y2) > 0.5 * p.H) {
+                code = kEvExit;
+                lost = true;
+            }
+        }
+        if (lost) {
+            double o[6];
+            reinject(p, (uint64_t)i, n, o);
+            xs[i] = (T)o[0]; xs[Npad + i] = (T)o[1]; xs[2 * Npad + i] = (T)o[2];
+            vs[i] = (T)o[3]; vs[Npad + i] = (T)o[4]; vs[2 * Npad + i] = (T)o[5];
+        } else {
+            xs[i] = y0; xs[Npad + i] = y1; xs[2 * Npad + i] = y2;
+            vs[i] = v0; vs[Npad + i] = v1; vs[2 * Npad + i] = v2;
+        }
+        ev[i] = code | (coll ? kEvCollBit : 0);
+    }
+    // wave totals of exits and collisions
+    const unsigned long long ex = __ballot(code == kEvExit);
+    const unsigned long long cl = __ballot(coll);
+    if ((threadIdx.x & 63) == 0) {
+        if (ex) atomicAdd(&ctl->cnt[0], (unsigned long long)__popcll(ex));
+        if (cl) atomicAdd(&ctl->cnt[1], (unsigned long long)__popcll(cl));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Finalize: one wave, lane d handles grain d.
+__global__ __launch_bounds__(64) void finalize_kernel(FinalArgs f, DustSet ds,
+                                                      Ctl* __restrict__ ctl)
+{
+    const int d = threadIdx.x;
+    __shared__ double Qs[kMaxDust];
+    if (d < f.nd) Qs[d] = ctl->Q[d];
+    __syncthreads();
+    const long long n = ctl->step;
+    if (d < f.nd) {
+        const double Qn = Qs[d];
+        const double S0 = from_fixed(ctl->acc[d][0], kForceScale);
+        const double S1 = from_fixed(ctl->acc[d][1], kForceScale);
+        const double S2 = from_fixed(ctl->acc[d][2], kForceScale);
+        const double cntd = (double)(long long)ctl->acc[d][3];
+        const double P0 = from_fixed(ctl->acc[d][4], kMomScale);
+        const double P1 = from_fixed(ctl->acc[d][5], kMomScale);
+        const double P2 = from_fixed(ctl->acc[d][6], kMomScale);
+        for (int c = 0; c < 8; ++c) ctl->acc[d][c] = 0ull;
+
+        // charge update
+        const double psi = f.psi[d] * Qn;                     // e phi / kB Te
+        const double Ie = -f.Ie0[d] * (psi < 0.0 ? exp(psi) : 1.0 + psi);
+        double Qnew = Qn;
+        if (f.mode == 2) {
+            Qnew = Qn + f.w * cntd + Ie * f.dt;
+        } else if (f.mode == 1) {
+            const double chi = psi < 0.0 ? -psi * f.te_over_ti : 0.0;
+            const double s = f.s_oml;
+            const double br = s < 1e-6 ? 1.1283791670955125739 * (1.0 + chi)
+                                       : exp(-s * s) * 0.5641895835477562869 +
+                                             (s * s + 0.5 + chi) * erf(s) / s;
+            Qnew = Qn + (f.Ii0[d] * br + Ie) * f.dt;
+        }
+
+        // forces, SI
+        double F[12];
+        const double co = f.c_orbit * Qn;
+        F[0] = co * S0; F[1] = co * S1; F[2] = co * S2;
+        double px = 0.0, py = 0.0, pz = 0.0;
+        for (int q = 0; q < f.nd; ++q) {
+            if (q == d) continue;
+            const double rx = ds.pos[d][0] - ds.pos[q][0], ry = ds.pos[d][1] - ds.pos[q][1],
+                         rz = ds.pos[d][2] - ds.pos[q][2];
+            const double r2 = rx * rx + ry * ry + rz * rz;
+            const double k = Qs[q] / (r2 * sqrt(r2));
+            px += k * rx; py += k * ry; pz += k * rz;
+        }
+        const double cd = f.c_dd * Qn;
+        F[3] = cd * px; F[4] = cd * py; F[5] = cd * pz;
+        F[6] = f.c_coll * P0; F[7] = f.c_coll * P1; F[8] = f.c_coll * P2;
+        F[9] = 0.0; F[10] = 0.0; F[11] = f.c_ext * Qn;
+
+        bool bad = !(Qnew == Qnew) || (Qnew - Qnew != 0.0);
+        ctl->last[d][0] = Qn;
+        for (int c = 0; c < 12; ++c) {
+            ctl->last[d][1 + c] = F[c];
+            bad = bad || (F[c] - F[c] != 0.0);
+        }
+        ctl->last[d][13] = cntd;
+        if (n >= f.n_discard) {
+            ctl->sums[d][0] += Qn;
+            for (int c = 0; c < 12; ++c) ctl->sums[d][1 + c] += F[c];
+        }
+        ctl->Q[d] = Qnew;
+        if (bad) atomicOr(&ctl->status, kStNaN);
+    }
+    __syncthreads();
+    if (d == 0) {
+        ctl->last_exit = (long long)ctl->cnt[0];
+        ctl->last_coll = (long long)ctl->cnt[1];
+        ctl->cnt[0] = 0ull;
+        ctl->cnt[1] = 0ull;
+        if (n >= f.n_discard) ctl->nrec += 1;
+        ctl->step = n + 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Initial state: uniform in the cylinder outside every grain, velocities from
+// N((0,0,u), sig^2).  Padding slots get a far-away sentinel position that
+// contributes exactly zero to every pair sum.
+template <typename T>
+__global__ __launch_bounds__(256) void init_kernel(T* __restrict__ xs, T* __restrict__ vs,
+                                                   T* __restrict__ as, PushArgs p, DustSet ds,
+                                                   Ctl* __restrict__ ctl)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int Npad = p.Npad;
+    if (i >= Npad) return;
+    if (i >= p.N) {
+        const T far = (T)1.0e18;
+        xs[i] = far; xs[Npad + i] = far; xs[2 * Npad + i] = far;
+        vs[i] = 0; vs[Npad + i] = 0; vs[2 * Npad + i] = 0;
+        as[i] = 0; as[Npad + i] = 0; as[2 * Npad + i] = 0;
+        return;
+    }
+    double px = 0.0, py = 0.0, pz = 0.0;
+    bool ok = false;
+    for (uint64_t k = 0; k < 1000 && !ok; ++k) {
+        const U64x4 r = philox((uint64_t)i, 0, kInitPos, k, p.k0, p.k1);
+        const double rr = p.R * sqrt(unit(r.w[0]));
+        double sn, cs;
+        sincos(2.0 * kPi * unit(r.w[1]), &sn, &cs);
+        px = rr * cs;
+        py = rr * sn;
+        pz = p.H * (unit(r.w[2]) - 0.5);
+        ok = true;
+        for (int d = 0; d < ds.nd; ++d) {
+            const double a0 = px - ds.pos[d][0], a1 = py - ds.pos[d][1], a2 = pz - ds.pos[d][2];
+            if (a0 * a0 + a1 * a1 + a2 * a2 <= ds.rad2[d]) ok = false;
+        }
+    }
+    if (!ok) atomicOr(&ctl->status, kStPlace);
+    const U64x4 g = philox((uint64_t)i, 0, kInitVel, 0, p.k0, p.k1);
+    double g1, g2, g3, g4;
+    gauss2(unit(g.w[0]), unit(g.w[1]), g1, g2);
+    gauss2(unit(g.w[2]), unit(g.w[3]), g3, g4);
+    xs[i] = (T)px; xs[Npad + i] = (T)py; xs[2 * Npad + i] = (T)pz;
+    vs[i] = (T)(p.sig * g1); vs[Npad + i] = (T)(p.sig * g2); vs[2 * Npad + i] = (T)(p.ubar + p.sig * g3);
+    as[i] = 0; as[Npad + i] = 0; as[2 * Npad + i] = 0;
+}
+
+__global__ void rng_kernel(uint64_t k0, uint64_t k1, uint64_t c0, uint64_t c1, uint64_t c2,
+                           uint64_t c3, uint64_t* out)
+{
+    if (threadIdx.x == 0) {
+        const U64x4 r = philox(c0, c1, c2, c3, k0, k1);
+        for (int k = 0; k < 4; ++k) out[k] = r.w[k];
+    }
+}
+
+}  // namespace odk

@@ -1,0 +1,600 @@
+// odust.hip -- host runtime and C-ABI of libodust (declarations and the
+// meaning of every argument: include/odust.h).
+//
+// One od_system owns, on one HIP stream:
+//   x, v, a   [3][Npad] structure-of-arrays state, float (FP32 mode) or double
+//             (FP64 mode); Npad = N rounded up to the pair tile, padding slots
+//             parked at a far-away sentinel;
+//   ev        [Npad] per-ion event byte of the last step;
+//   ctl       small control block (charges, int64 fixed-point accumulators,
+//             last-step record, running sums, step counter, status word).
+// All per-step state stays on the device; a step is three launches (pair
+// forces, push, finalize) and needs no host synchronisation.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/odust.h"
+#include "kernels.hpp"
+
+namespace {
+
+constexpr double kQE = 1.602176634e-19;
+constexpr double kKB = 1.380649e-23;
+constexpr double kEPS0 = 8.8541878128e-12;
+constexpr double kME = 9.1093837015e-31;
+constexpr double kPI = 3.14159265358979323846;
+
+constexpr int kPairBlock = 256;
+constexpr int kPairTile = 256;
+constexpr int kPad = 256;
+
+thread_local std::string g_err;
+
+od_status fail(od_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIPCHK(expr)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(OD_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));    \
+    } while (0)
+
+uint64_t prob_to_threshold(double p)
+{
+    if (!(p > 0.0)) return 0;
+    const double t = p * 18446744073709551616.0;
+    if (t >= 18446744073709551615.0) return ~0ull;
+    return (uint64_t)t;
+}
+
+double normal_cdf(double t) { return 0.5 * std::erfc(-t / std::sqrt(2.0)); }
+double normal_pdf(double t) { return std::exp(-0.5 * t * t) / std::sqrt(2.0 * kPI); }
+
+}  // namespace
+
+struct od_system {
+    hipStream_t stream = nullptr;
+    od_allocator alloc{};
+    bool custom_alloc = false;
+    od_plasma pl{};
+    od_sim sim{};
+    int nd = 0;
+    od_dust dust[OD_MAX_DUST]{};
+    int prec = 0;
+    int64_t N = 0, Npad = 0;
+    size_t esz = 4;
+    // units
+    double lam = 0, wpi = 0, cs = 0;
+    odk::DustSet ds{};
+    odk::PairArgs pa{};
+    odk::PushArgs pu{};
+    odk::FinalArgs fa{};
+    // device memory
+    void* x = nullptr;
+    void* v = nullptr;
+    void* a = nullptr;
+    uint8_t* ev = nullptr;
+    odk::Ctl* ctl = nullptr;
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> evpool;
+    std::vector<std::pair<int, int>> marks[3];   // (start idx, stop idx) per class
+    size_t evnext = 0;
+};
+
+namespace {
+
+void* dev_alloc(od_system* s, size_t bytes)
+{
+    if (s->custom_alloc) return s->alloc.alloc(s->alloc.ctx, bytes);
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    return p;
+}
+
+void dev_free(od_system* s, void* p)
+{
+    if (!p) return;
+    if (s->custom_alloc)
+        s->alloc.release(s->alloc.ctx, p);
+    else
+        (void)hipFree(p);
+}
+
+od_status check_params(const od_plasma* pl, const od_sim* sim, const od_dust* dust, int nd)
+{
+    if (!pl || !sim) return fail(OD_EINVAL, "null plasma or sim");
+    if (nd < 0 || nd > OD_MAX_DUST) return fail(OD_EINVAL, "n_dust %d out of [0,%d]", nd, OD_MAX_DUST);
+    if (nd > 0 && !dust) return fail(OD_EINVAL, "null dust array");
+    if (!(pl->T_e > 0) || !(pl->T_i > 0) || !(pl->n_inf > 0) || !(pl->m_i > 0))
+        return fail(OD_EINVAL, "temperatures, density and ion mass must be positive");
+    if (!(pl->mach >= 0) || !(pl->nu_in >= 0) || std::isinf(pl->E_ext))
+        return fail(OD_EINVAL, "mach and nu_in must be >= 0 and E_ext finite or NaN");
+    if (!(sim->R > 0) || !(sim->H > 0) || !(sim->dt > 0))
+        return fail(OD_EINVAL, "R, H and dt must be positive");
+    if (sim->n_ions < 2 || sim->n_ions > (int64_t)1 << 30)
+        return fail(OD_EINVAL, "n_ions %lld out of [2, 2^30]", (long long)sim->n_ions);
+    if (sim->n_discard < 0) return fail(OD_EINVAL, "n_discard must be >= 0");
+    if (sim->charge_mode < 0 || sim->charge_mode > 2) return fail(OD_EINVAL, "bad charge_mode");
+    if (sim->precision != OD_PREC_FP32 && sim->precision != OD_PREC_FP64)
+        return fail(OD_EINVAL, "bad precision");
+    if (sim->flags & ~(OD_FLAG_LITERAL_SIDE | OD_FLAG_NO_ION_ION)) return fail(OD_EINVAL, "unknown flags");
+    if (sim->reserved != 0) return fail(OD_EINVAL, "reserved must be 0");
+    for (int d = 0; d < nd; ++d) {
+        const od_dust& g = dust[d];
+        if (!(g.radius > 0) || !std::isfinite(g.q0) || !std::isfinite(g.x) || !std::isfinite(g.y) ||
+            !std::isfinite(g.z))
+            return fail(OD_EINVAL, "grain %d: bad radius, charge or position", d);
+        const double rho = std::sqrt(g.x * g.x + g.y * g.y);
+        if (rho + g.radius >= sim->R || std::fabs(g.z) + g.radius >= 0.5 * sim->H)
+            return fail(OD_EINVAL, "grain %d crosses the domain boundary", d);
+        for (int q = 0; q < d; ++q) {
+            const double dx = g.x - dust[q].x, dy = g.y - dust[q].y, dz = g.z - dust[q].z;
+            if (std::sqrt(dx * dx + dy * dy + dz * dz) <= g.radius + dust[q].radius)
+                return fail(OD_EINVAL, "grains %d and %d overlap", q, d);
+        }
+    }
+    return OD_OK;
+}
+
+// SI -> dimensionless constants of every kernel.
+void derive(od_system* s)
+{
+    const od_plasma& P = s->pl;
+    const od_sim& S = s->sim;
+    const double lam = std::sqrt(kEPS0 * kKB * P.T_e / (P.n_inf * kQE * kQE));
+    const double wpi = std::sqrt(P.n_inf * kQE * kQE / (kEPS0 * P.m_i));
+    const double cs = lam * wpi;
+    s->lam = lam;
+    s->wpi = wpi;
+    s->cs = cs;
+    const double sig = std::sqrt(P.T_i / P.T_e);
+    const double ubar = P.mach;
+    const double R = S.R / lam, H = S.H / lam, dt = S.dt * wpi, nu = P.nu_in / wpi;
+    const double nl3 = P.n_inf * lam * lam * lam;          // ions per Debye cube
+    const double Vt = kPI * R * R * H;
+    const double w = nl3 * Vt / (double)S.n_ions;           // ions per superparticle
+    double Ez, E_si;
+    if (std::isnan(P.E_ext)) {
+        Ez = nu > 0 ? nu * ubar : 0.0;
+        E_si = P.nu_in > 0 ? P.m_i * P.nu_in * ubar * cs / kQE : 0.0;
+    } else {
+        E_si = P.E_ext;
+        Ez = kQE * P.E_ext / (P.m_i * lam * wpi * wpi);
+    }
+    const double Pc = -std::expm1(-nu * dt);
+
+    odk::DustSet& ds = s->ds;
+    ds.nd = s->nd;
+    for (int d = 0; d < s->nd; ++d) {
+        ds.pos[d][0] = s->dust[d].x / lam;
+        ds.pos[d][1] = s->dust[d].y / lam;
+        ds.pos[d][2] = s->dust[d].z / lam;
+        const double a = s->dust[d].radius / lam;
+        ds.rad2[d] = a * a;
+    }
+
+    odk::PairArgs& pa = s->pa;
+    pa.N = (int)s->N;
+    pa.Npad = (int)s->Npad;
+    pa.nd = s->nd;
+    pa.ion_ion = (S.flags & OD_FLAG_NO_ION_ION) ? 0 : 1;
+    pa.Cd = Vt / (4.0 * kPI * (double)S.n_ions);
+    pa.C = (float)pa.Cd;
+    pa.Kq = 1.0 / (4.0 * kPI * nl3);
+    pa.Ez = Ez;
+
+    // face inflows per unit density (Appendix B), dimensionless
+    auto face = [&](double m) { return m * normal_cdf(m / sig) + sig * normal_pdf(m / sig); };
+    const double Jb = kPI * R * R * face(ubar);
+    const double Jt = kPI * R * R * face(-ubar);
+    const double Js = 2.0 * kPI * R * H * sig / std::sqrt(2.0 * kPI);
+    const double J = Jb + Jt + Js;
+
+    odk::PushArgs& pu = s->pu;
+    pu.N = (int)s->N;
+    pu.Npad = (int)s->Npad;
+    pu.nd = s->nd;
+    pu.flags = S.flags;
+    pu.dt = dt;
+    pu.sig = sig;
+    pu.ubar = ubar;
+    pu.R = R;
+    pu.H = H;
+    pu.k0 = S.seed;
+    pu.k1 = S.system_id;
+    pu.Tc = prob_to_threshold(Pc);
+    pu.Tb = prob_to_threshold(Jb / J);
+    pu.Tbt = prob_to_threshold((Jb + Jt) / J);
+
+    odk::FinalArgs& fa = s->fa;
+    fa.nd = s->nd;
+    fa.mode = S.charge_mode;
+    fa.n_discard = S.n_discard;
+    fa.dt = dt;
+    fa.w = w;
+    const double ve = std::sqrt(8.0 * kKB * P.T_e / (kPI * kME));
+    const double vt = std::sqrt(2.0 * kKB * P.T_i / P.m_i);
+    for (int d = 0; d < s->nd; ++d) {
+        const double a = s->dust[d].radius;
+        fa.Ie0[d] = kPI * a * a * P.n_inf * ve / wpi;
+        fa.Ii0[d] = kPI * a * a * P.n_inf * vt / wpi;
+        fa.psi[d] = kQE * kQE / (4.0 * kPI * kEPS0 * a * kKB * P.T_e);
+    }
+    fa.s_oml = ubar * cs / vt;
+    fa.te_over_ti = P.T_e / P.T_i;
+    const double k_e2 = kQE * kQE / (4.0 * kPI * kEPS0 * lam * lam);
+    fa.c_orbit = w * k_e2;
+    fa.c_dd = k_e2;
+    fa.c_coll = w * P.m_i * cs / S.dt;
+    fa.c_ext = kQE * E_si;
+}
+
+hipEvent_t next_event(od_system* s)
+{
+    if (s->evnext == s->evpool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        s->evpool.push_back(e);
+    }
+    return s->evpool[s->evnext++];
+}
+
+od_status launch_step(od_system* s)
+{
+    const int gp = (int)(s->Npad / kPairBlock);
+    const int gq = (int)((s->N + 255) / 256);
+    for (int k = 0; k < 3; ++k) {
+        int e0 = -1, e1 = -1;
+        if (s->timing) {
+            e0 = (int)s->evnext;
+            hipEvent_t e = next_event(s);
+            if (!e) return fail(OD_EDEVICE, "hipEventCreate failed");
+            HIPCHK(hipEventRecord(e, s->stream));
+        }
+        if (k == 0) {
+            if (s->prec == OD_PREC_FP32)
+                odk::pair_forces_f32<kPairBlock, kPairTile><<<gp, kPairBlock, 0, s->stream>>>(
+                    (const float*)s->x, (float*)s->a, s->pa, s->ds, s->ctl);
+            else
+                odk::pair_forces_f64<kPairBlock, kPairTile><<<gp, kPairBlock, 0, s->stream>>>(
+                    (const double*)s->x, (double*)s->a, s->pa, s->ds, s->ctl);
+        } else if (k == 1) {
+            if (s->prec == OD_PREC_FP32)
+                odk::push_kernel<float><<<gq, 256, 0, s->stream>>>(
+                    (float*)s->x, (float*)s->v, (const float*)s->a, s->ev, s->pu, s->ds, s->ctl);
+            else
+                odk::push_kernel<double><<<gq, 256, 0, s->stream>>>(
+                    (double*)s->x, (double*)s->v, (const double*)s->a, s->ev, s->pu, s->ds, s->ctl);
+        } else {
+            odk::finalize_kernel<<<1, 64, 0, s->stream>>>(s->fa, s->ds, s->ctl);
+        }
+        HIPCHK(hipGetLastError());
+        if (s->timing) {
+            e1 = (int)s->evnext;
+            hipEvent_t e = next_event(s);
+            if (!e) return fail(OD_EDEVICE, "hipEventCreate failed");
+            HIPCHK(hipEventRecord(e, s->stream));
+            s->marks[k].push_back({e0, e1});
+        }
+    }
+    return OD_OK;
+}
+
+od_status read_status(od_system* s)
+{
+    int st = 0;
+    HIPCHK(hipMemcpyAsync(&st, &s->ctl->status, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    if (st & odk::kStPlace) return fail(OD_ESTATE, "an ion could not be placed outside the grains");
+    if (st & odk::kStNaN) return fail(OD_ENUMERIC, "non-finite charge or force on the device");
+    if (st & odk::kStOverflow) return fail(OD_ENUMERIC, "fixed-point accumulator overflow");
+    return OD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* od_last_error(void) { return g_err.c_str(); }
+
+od_status od_init_system(const od_plasma* plasma, const od_sim* sim, const od_dust* dust,
+                         int32_t n_dust, void* hip_stream, const od_allocator* allocator,
+                         od_system** out)
+{
+    if (!out) return fail(OD_EINVAL, "null out");
+    *out = nullptr;
+    od_status st = check_params(plasma, sim, dust, n_dust);
+    if (st != OD_OK) return st;
+    if (allocator && (!allocator->alloc || !allocator->release))
+        return fail(OD_EINVAL, "allocator needs alloc and release");
+    od_system* s = new (std::nothrow) od_system();
+    if (!s) return fail(OD_ENOMEM, "host allocation failed");
+    s->stream = (hipStream_t)hip_stream;
+    if (allocator) {
+        s->alloc = *allocator;
+        s->custom_alloc = true;
+    }
+    s->pl = *plasma;
+    s->sim = *sim;
+    s->nd = n_dust;
+    for (int d = 0; d < n_dust; ++d) s->dust[d] = dust[d];
+    s->prec = sim->precision;
+    s->esz = s->prec == OD_PREC_FP32 ? 4 : 8;
+    s->N = sim->n_ions;
+    s->Npad = (s->N + kPad - 1) / kPad * kPad;
+    derive(s);
+
+    const size_t vec = 3 * (size_t)s->Npad * s->esz;
+    s->x = dev_alloc(s, vec);
+    s->v = dev_alloc(s, vec);
+    s->a = dev_alloc(s, vec);
+    s->ev = (uint8_t*)dev_alloc(s, (size_t)s->Npad);
+    s->ctl = (odk::Ctl*)dev_alloc(s, sizeof(odk::Ctl));
+    if (!s->x || !s->v || !s->a || !s->ev || !s->ctl) {
+        od_destroy(s);
+        return fail(OD_ENOMEM, "device allocation of %zu bytes failed", 3 * vec);
+    }
+    odk::Ctl h{};
+    std::memset(&h, 0, sizeof h);
+    for (int d = 0; d < n_dust; ++d) h.Q[d] = dust[d].q0 / kQE;
+    hipError_t e = hipMemcpyAsync(s->ctl, &h, sizeof h, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s->ev, 0, (size_t)s->Npad, s->stream);
+    if (e != hipSuccess) {
+        od_destroy(s);
+        return fail(OD_EDEVICE, "upload failed: %s", hipGetErrorString(e));
+    }
+    const int gi = (int)((s->Npad + 255) / 256);
+    if (s->prec == OD_PREC_FP32)
+        odk::init_kernel<float><<<gi, 256, 0, s->stream>>>((float*)s->x, (float*)s->v, (float*)s->a,
+                                                           s->pu, s->ds, s->ctl);
+    else
+        odk::init_kernel<double><<<gi, 256, 0, s->stream>>>((double*)s->x, (double*)s->v,
+                                                            (double*)s->a, s->pu, s->ds, s->ctl);
+    e = hipGetLastError();
+    if (e != hipSuccess) {
+        od_destroy(s);
+        return fail(OD_EDEVICE, "init kernel launch failed: %s", hipGetErrorString(e));
+    }
+    st = read_status(s);
+    if (st != OD_OK) {
+        od_destroy(s);
+        return st;
+    }
+    *out = s;
+    return OD_OK;
+}
+
+od_status od_step(od_system* s, int64_t n_steps)
+{
+    if (!s) return fail(OD_EINVAL, "null system");
+    if (n_steps < 0) return fail(OD_EINVAL, "n_steps < 0");
+    for (int64_t k = 0; k < n_steps; ++k) {
+        od_status st = launch_step(s);
+        if (st != OD_OK) return st;
+    }
+    return OD_OK;
+}
+
+od_status od_sync(od_system* s)
+{
+    if (!s) return fail(OD_EINVAL, "null system");
+    return read_status(s);
+}
+
+od_status od_get_dust_charges(od_system* s, double* q_now, double* q_avg)
+{
+    if (!s) return fail(OD_EINVAL, "null system");
+    odk::Ctl h;
+    HIPCHK(hipMemcpyAsync(&h, s->ctl, sizeof h, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    for (int d = 0; d < s->nd; ++d) {
+        if (q_now) q_now[d] = h.Q[d] * kQE;
+        if (q_avg) q_avg[d] = h.nrec ? h.sums[d][0] / (double)h.nrec * kQE : 0.0;
+    }
+    return read_status(s);
+}
+
+od_status od_get_dust_forces(od_system* s, int32_t which, double* f)
+{
+    if (!s || !f) return fail(OD_EINVAL, "null argument");
+    if (which != 0 && which != 1) return fail(OD_EINVAL, "which must be 0 or 1");
+    odk::Ctl h;
+    HIPCHK(hipMemcpyAsync(&h, s->ctl, sizeof h, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    for (int d = 0; d < s->nd; ++d)
+        for (int c = 0; c < 12; ++c) {
+            if (which == 0)
+                f[12 * d + c] = h.last[d][1 + c];
+            else
+                f[12 * d + c] = h.nrec ? h.sums[d][1 + c] / (double)h.nrec : 0.0;
+        }
+    return read_status(s);
+}
+
+void od_destroy(od_system* s)
+{
+    if (!s) return;
+    if (s->stream || true) (void)hipStreamSynchronize(s->stream);
+    dev_free(s, s->x);
+    dev_free(s, s->v);
+    dev_free(s, s->a);
+    dev_free(s, s->ev);
+    dev_free(s, s->ctl);
+    for (hipEvent_t e : s->evpool) (void)hipEventDestroy(e);
+    delete s;
+}
+
+od_status od_get_units(od_system* s, double* u)
+{
+    if (!s || !u) return fail(OD_EINVAL, "null argument");
+    u[0] = s->lam;
+    u[1] = 1.0 / s->wpi;
+    u[2] = s->cs;
+    u[3] = s->lam * s->wpi * s->wpi;
+    return OD_OK;
+}
+
+od_status od_get_sizes(od_system* s, int64_t* o)
+{
+    if (!s || !o) return fail(OD_EINVAL, "null argument");
+    o[0] = s->N;
+    o[1] = s->nd;
+    o[2] = s->prec;
+    o[3] = s->Npad;
+    return OD_OK;
+}
+
+static od_status copy_soa_out(od_system* s, const void* dev, void* host)
+{
+    const size_t row = (size_t)s->N * s->esz;
+    const size_t drow = (size_t)s->Npad * s->esz;
+    for (int c = 0; c < 3; ++c)
+        HIPCHK(hipMemcpyAsync((char*)host + c * row, (const char*)dev + c * drow, row,
+                              hipMemcpyDeviceToHost, s->stream));
+    return OD_OK;
+}
+
+od_status od_get_state(od_system* s, void* x, void* v, double* q, int64_t* step)
+{
+    if (!s) return fail(OD_EINVAL, "null system");
+    od_status st;
+    if (x && (st = copy_soa_out(s, s->x, x)) != OD_OK) return st;
+    if (v && (st = copy_soa_out(s, s->v, v)) != OD_OK) return st;
+    odk::Ctl h;
+    HIPCHK(hipMemcpyAsync(&h, s->ctl, sizeof h, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    if (q)
+        for (int d = 0; d < s->nd; ++d) q[d] = h.Q[d] * kQE;
+    if (step) *step = h.step;
+    return OD_OK;
+}
+
+od_status od_set_state(od_system* s, const void* x, const void* v, const double* q, int64_t step)
+{
+    if (!s) return fail(OD_EINVAL, "null system");
+    if (step < 0) return fail(OD_EINVAL, "step < 0");
+    const int64_t N = s->N;
+    auto val = [&](const void* p, int64_t k) {
+        return s->prec == OD_PREC_FP32 ? (double)((const float*)p)[k] : ((const double*)p)[k];
+    };
+    for (const void* p : {x, v}) {
+        if (!p) continue;
+        for (int64_t k = 0; k < 3 * N; ++k)
+            if (!std::isfinite(val(p, k))) return fail(OD_ENUMERIC, "non-finite state value at %lld", (long long)k);
+    }
+    if (x) {
+        for (int64_t i = 0; i < N; ++i) {
+            const double px = val(x, i), py = val(x, N + i), pz = val(x, 2 * N + i);
+            for (int d = 0; d < s->nd; ++d) {
+                const double a0 = px - s->ds.pos[d][0], a1 = py - s->ds.pos[d][1], a2 = pz - s->ds.pos[d][2];
+                if (a0 * a0 + a1 * a1 + a2 * a2 <= s->ds.rad2[d])
+                    return fail(OD_ESTATE, "ion %lld lies inside grain %d", (long long)i, d);
+            }
+        }
+    }
+    if (q)
+        for (int d = 0; d < s->nd; ++d)
+            if (!std::isfinite(q[d])) return fail(OD_ENUMERIC, "non-finite charge");
+    const size_t row = (size_t)N * s->esz;
+    const size_t drow = (size_t)s->Npad * s->esz;
+    for (int c = 0; c < 3; ++c) {
+        if (x)
+            HIPCHK(hipMemcpyAsync((char*)s->x + c * drow, (const char*)x + c * row, row,
+                                  hipMemcpyHostToDevice, s->stream));
+        if (v)
+            HIPCHK(hipMemcpyAsync((char*)s->v + c * drow, (const char*)v + c * row, row,
+                                  hipMemcpyHostToDevice, s->stream));
+    }
+    odk::Ctl h;
+    HIPCHK(hipMemcpyAsync(&h, s->ctl, sizeof h, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    if (q)
+        for (int d = 0; d < s->nd; ++d) h.Q[d] = q[d] / kQE;
+    h.step = step;
+    HIPCHK(hipMemcpyAsync(s->ctl, &h, sizeof h, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return OD_OK;
+}
+
+od_status od_get_accelerations(od_system* s, void* a)
+{
+    if (!s || !a) return fail(OD_EINVAL, "null argument");
+    od_status st = copy_soa_out(s, s->a, a);
+    if (st != OD_OK) return st;
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return OD_OK;
+}
+
+od_status od_get_step_events(od_system* s, uint8_t* ev, int64_t* n_abs, int64_t* n_exit, int64_t* n_coll)
+{
+    if (!s) return fail(OD_EINVAL, "null system");
+    if (ev) HIPCHK(hipMemcpyAsync(ev, s->ev, (size_t)s->N, hipMemcpyDeviceToHost, s->stream));
+    odk::Ctl h;
+    HIPCHK(hipMemcpyAsync(&h, s->ctl, sizeof h, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    if (n_abs)
+        for (int d = 0; d < s->nd; ++d) n_abs[d] = (int64_t)h.last[d][13];
+    if (n_exit) *n_exit = h.last_exit;
+    if (n_coll) *n_coll = h.last_coll;
+    return OD_OK;
+}
+
+od_status od_rng_block(uint64_t seed, uint64_t system, const uint64_t* ctr, uint64_t* out)
+{
+    if (!ctr || !out) return fail(OD_EINVAL, "null argument");
+    uint64_t* d = nullptr;
+    HIPCHK(hipMalloc(&d, 4 * sizeof(uint64_t)));
+    odk::rng_kernel<<<1, 64>>>(seed, system, ctr[0], ctr[1], ctr[2], ctr[3], d);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpy(out, d, 4 * sizeof(uint64_t), hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(OD_EDEVICE, "rng kernel: %s", hipGetErrorString(e));
+    return OD_OK;
+}
+
+od_status od_set_timing(od_system* s, int32_t enable)
+{
+    if (!s) return fail(OD_EINVAL, "null system");
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->timing = enable != 0;
+    for (auto& m : s->marks) m.clear();
+    s->evnext = 0;
+    return OD_OK;
+}
+
+od_status od_get_kernel_times(od_system* s, double* ms, int64_t* launches)
+{
+    if (!s) return fail(OD_EINVAL, "null system");
+    HIPCHK(hipStreamSynchronize(s->stream));
+    for (int k = 0; k < 3; ++k) {
+        double tot = 0.0;
+        for (auto& m : s->marks[k]) {
+            float t = 0.0f;
+            HIPCHK(hipEventElapsedTime(&t, s->evpool[m.first], s->evpool[m.second]));
+            tot += t;
+        }
+        if (ms) ms[k] = tot;
+        if (launches) launches[k] = (int64_t)s->marks[k].size();
+        s->marks[k].clear();
+    }
+    s->evnext = 0;
+    return OD_OK;
+}
+
+}  // extern "C"
