@@ -44,15 +44,14 @@ def cpu_baseline(w, sysm, target_s: float):
     lam, cs = o.derived["lam"], o.derived["cs"]
     o.set_state(x.T.astype(np.float64) * lam, v.T.astype(np.float64) * cs, q, step)
     rng = np.random.default_rng(0)
-    m = 64
-    t0 = time.perf_counter()
-    o.accel_subset(rng.choice(w.n_ions, size=m, replace=False))
-    t1 = time.perf_counter() - t0
-    m2 = int(max(64, min(w.n_ions, m * target_s / max(t1, 1e-3))))
-    idx = rng.choice(w.n_ions, size=m2, replace=False)
-    t0 = time.perf_counter()
-    o.accel_subset(idx)
-    dt = time.perf_counter() - t0
+    o.accel_subset(rng.choice(w.n_ions, size=16, replace=False))      # threads up, caches warm
+    order = rng.permutation(w.n_ions)
+    m2, chunk, dt = 0, 256, 0.0
+    while dt < target_s and m2 + chunk <= w.n_ions:
+        t0 = time.perf_counter()
+        o.accel_subset(order[m2:m2 + chunk])
+        dt += time.perf_counter() - t0
+        m2 += chunk
     pairs = m2 * (w.n_ions - 1)
     pps = pairs / dt
     return {
@@ -76,6 +75,8 @@ def main():
     ap.add_argument("--fp64", action="store_true", help="FP64 state and pair forces")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a plain 256 MiB device copy first (reference for memory counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -88,6 +89,16 @@ def main():
     from paper_2205_06557_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        flush = torch.empty(1 << 30, dtype=torch.uint8, device="cuda").fill_(2)   # evicts the 256 MB MALL
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("[bench] calibration copy: 268435456 B read, 268435456 B written", file=sys.stderr,
+              flush=True)
+        del src, dst, flush
     w = W.two_grain_wake().with_(n_ions=args.n_ions)
     prec = B.PREC_FP64 if args.fp64 else B.PREC_FP32
     sysm = B.System(w, precision=prec)
@@ -114,6 +125,7 @@ def main():
     pair_ms = kt["pair"][0] / max(kt["pair"][1], 1)
     push_ms = kt["push"][0] / max(kt["push"][1], 1)
     fin_ms = kt["finalize"][0] / max(kt["finalize"][1], 1)
+    rein_ms = kt["reinject"][0] / max(kt["reinject"][1], 1)
     achieved = FLOP_PER_PAIR * N * (N - 1) / (pair_ms * 1e-3)
     push_gbs = push_bytes_per_ion(prec) * N / (push_ms * 1e-3)
     q, _ = sysm.charges()
@@ -154,7 +166,7 @@ def main():
             "bytes_per_ion": push_bytes_per_ion(prec),
             "launch_ms": push_ms,
         },
-        "kernel_ms": {"pair": pair_ms, "push": push_ms, "finalize": fin_ms},
+        "kernel_ms": {"pair": pair_ms, "push": push_ms, "reinject": rein_ms, "finalize": fin_ms},
         "dust_charge_e": [float(x) / 1.602176634e-19 for x in q],
     }
     if not args.no_cpu:

@@ -185,9 +185,9 @@ od_status od_rng_block(uint64_t seed, uint64_t system, const uint64_t* ctr_host,
 
 /* Kernel timing with HIP events on the system's stream.  While enabled,
  * od_step brackets every launch; od_get_kernel_times synchronises and
- * returns, per kernel class {0 pair forces, 1 push, 2 finalize}, the summed
- * milliseconds ms_host[3] and launch counts launches_host[3] since enabling,
- * then resets them. */
+ * returns, per kernel class {0 pair forces, 1 push, 2 reinjection,
+ * 3 finalize}, the summed milliseconds ms_host[4] and launch counts
+ * launches_host[4] since enabling, then resets them. */
 od_status od_set_timing(od_system* sys, int32_t enable);
 od_status od_get_kernel_times(od_system* sys, double* ms_host, int64_t* launches_host);
 

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libodust.so")
 OD_OK, OD_EINVAL, OD_EDEVICE, OD_ENUMERIC, OD_ESTATE, OD_ENOMEM = 0, -1, -2, -3, -4, -5
 PREC_FP32, PREC_FP64 = 0, 1
 EV_NONE, EV_EXIT, EV_ABS_BASE, EV_COLL_BIT = 0, 1, 2, 0x80
-KERNEL_CLASSES = ("pair", "push", "finalize")
+KERNEL_CLASSES = ("pair", "push", "reinject", "finalize")
 
 
 class OdError(RuntimeError):
@@ -240,7 +240,7 @@ class System:
         _check(lib().od_set_timing(self._h, 1 if enable else 0))
 
     def kernel_times(self):
-        ms = np.zeros(3)
-        n = np.zeros(3, dtype=np.int64)
+        ms = np.zeros(len(KERNEL_CLASSES))
+        n = np.zeros(len(KERNEL_CLASSES), dtype=np.int64)
         _check(lib().od_get_kernel_times(self._h, _ptr(ms), _ptr(n, C.c_int64)))
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_CLASSES)}

@@ -31,7 +31,7 @@ constexpr double kMomScale = 4294967296.0;      // 2^32: absorbed velocity sums,
 // Layout of one system's control block (device memory, int64/double words).
 struct Ctl {
     unsigned long long acc[kMaxDust][8];   // [0..2] Eq.(1) sum, [3] absorbed count, [4..6] sum v
-    unsigned long long cnt[4];             // [0] exits, [1] collisions
+    unsigned long long cnt[4];             // [0] exits, [1] collisions, [2] lost-list length
     double Q[kMaxDust];                    // charge, e
     double last[kMaxDust][16];             // [0] Q^n, [1..12] F parts (SI), [13] absorbed count
     double sums[kMaxDust][16];             // running sums over recorded steps

@@ -6,8 +6,10 @@
 //       over all ions, reduced per block and added to int64 fixed-point
 //       accumulators.
 //   push_kernel<T>      kick, charge exchange, drift, absorption test against
-//       every grain along the drift segment, exit test, reinjection on the
-//       boundary (Appendix B), per-ion event byte.
+//       every grain along the drift segment, exit test, per-ion event byte;
+//       lost ions are appended to a list.
+//   reinject_kernel<T>  new boundary position and velocity for every listed
+//       ion (Appendix B).
 //   finalize_kernel     one wave: charge update (the three charging models of
 //       Section 2), the four force parts of Eqs. (1)-(4) in SI, recording,
 //       time averages, clearing of the accumulators, step counter.
@@ -263,8 +265,9 @@ __device__ double flux_speed(double uu, double m, double s)
         const double slope = -v * npdf(t) / s;
         double nv = 0.5 * (lo + hi);
         if (slope < 0.0) {
+            // a converged step lands on the bracket end it just moved: keep it
             const double cand = v - g / slope;
-            if (cand > lo && cand < hi) nv = cand;
+            if (cand >= lo && cand <= hi) nv = cand;
         }
         const bool done = fabs(nv - v) <= 1e-13 * s;
         v = nv;
@@ -311,13 +314,15 @@ __device__ void reinject(const PushArgs& p, uint64_t ion, uint64_t n, double o[6
 template <typename T>
 __global__ __launch_bounds__(256) void push_kernel(T* __restrict__ xs, T* __restrict__ vs,
                                                    const T* __restrict__ as,
-                                                   uint8_t* __restrict__ ev, PushArgs p,
+                                                   uint8_t* __restrict__ ev,
+                                                   int* __restrict__ lost_list, PushArgs p,
                                                    DustSet ds, Ctl* __restrict__ ctl)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
     const int Npad = p.Npad;
     const uint64_t n = (uint64_t)ctl->step;
     bool coll = false;
+    bool lost = false;
     uint8_t code = kEvNone;
     if (i < p.N) {
         const T dt = (T)p.dt;
@@ -349,26 +354,34 @@ __global__ __launch_bounds__(256) void push_kernel(T* __restrict__ xs, T* __rest
         for (int d = 0; d < ds.nd; ++d) {
             const double s0 = (double)x0 - ds.pos[d][0], s1 = (double)x1 - ds.pos[d][1],
                          s2 = (double)x2 - ds.pos[d][2];
+            const double a2 = ds.rad2[d];
             const double ss = s0 * s0 + s1 * s1 + s2 * s2;
             const double sD = s0 * D0 + s1 * D1 + s2 * D2;
-            double th;
+            // squared closest approach of the segment, without a division:
+            // at the start if moving away, at the end if the foot of the
+            // perpendicular lies beyond it, else ss - sD^2/DD (scaled by DD)
             bool in;
-            if (DD > 0.0) {
-                const double tc = fmin(fmax(-sD / DD, 0.0), 1.0);
-                const double c0 = s0 + tc * D0, c1 = s1 + tc * D1, c2 = s2 + tc * D2;
-                in = c0 * c0 + c1 * c1 + c2 * c2 <= ds.rad2[d];
-                const double disc = fmax(sD * sD - DD * (ss - ds.rad2[d]), 0.0);
-                th = fmax((-sD - sqrt(disc)) / DD, 0.0);
+            if (DD == 0.0 || sD >= 0.0) {
+                in = ss <= a2;
+            } else if (-sD >= DD) {
+                const double e0 = (double)y0 - ds.pos[d][0], e1 = (double)y1 - ds.pos[d][1],
+                             e2 = (double)y2 - ds.pos[d][2];
+                in = e0 * e0 + e1 * e1 + e2 * e2 <= a2;
             } else {
-                in = ss <= ds.rad2[d];
-                th = 0.0;
+                in = ss * DD - sD * sD <= a2 * DD;
             }
-            if (in && th < tbest) {
-                tbest = th;
-                hit = d;
+            if (in) {   // rare: entry parameter of the first crossing
+                double th = 0.0;
+                if (DD > 0.0) {
+                    const double disc = fmax(sD * sD - DD * (ss - a2), 0.0);
+                    th = fmax((-sD - sqrt(disc)) / DD, 0.0);
+                }
+                if (th < tbest) {
+                    tbest = th;
+                    hit = d;
+                }
             }
         }
-        bool lost = false;
         if (hit >= 0) {
             code = (uint8_t)(kEvAbsBase + hit);
             atomicAdd(&ctl->acc[hit][3], 1ull);
@@ -383,23 +396,47 @@ __global__ __launch_bounds__(256) void push_kernel(T* __restrict__ xs, T* __rest
                 lost = true;
             }
         }
-        if (lost) {
-            double o[6];
-            reinject(p, (uint64_t)i, n, o);
-            xs[i] = (T)o[0]; xs[Npad + i] = (T)o[1]; xs[2 * Npad + i] = (T)o[2];
-            vs[i] = (T)o[3]; vs[Npad + i] = (T)o[4]; vs[2 * Npad + i] = (T)o[5];
-        } else {
-            xs[i] = y0; xs[Npad + i] = y1; xs[2 * Npad + i] = y2;
-            vs[i] = v0; vs[Npad + i] = v1; vs[2 * Npad + i] = v2;
-        }
+        // lost ions are overwritten by the reinjection kernel
+        xs[i] = y0; xs[Npad + i] = y1; xs[2 * Npad + i] = y2;
+        vs[i] = v0; vs[Npad + i] = v1; vs[2 * Npad + i] = v2;
         ev[i] = code | (coll ? kEvCollBit : 0);
     }
-    // wave totals of exits and collisions
+    // wave totals of exits and collisions; lost ions appended to the list
     const unsigned long long ex = __ballot(code == kEvExit);
     const unsigned long long cl = __ballot(coll);
-    if ((threadIdx.x & 63) == 0) {
+    const unsigned long long ls = __ballot(lost);
+    const int lane = threadIdx.x & 63;
+    unsigned long long base = 0;
+    if (lane == 0) {
         if (ex) atomicAdd(&ctl->cnt[0], (unsigned long long)__popcll(ex));
         if (cl) atomicAdd(&ctl->cnt[1], (unsigned long long)__popcll(cl));
+        if (ls) base = atomicAdd(&ctl->cnt[2], (unsigned long long)__popcll(ls));
+    }
+    if (ls) {
+        base = __shfl(base, 0, 64);
+        if (lost) {
+            const unsigned long long below = ls & ((1ull << lane) - 1ull);
+            lost_list[base + __popcll(below)] = i;
+        }
+    }
+}
+
+// Reinjection of the ions the push listed (Appendix B).  A fixed grid walks
+// the list, whose length the push left in the control block.
+template <typename T>
+__global__ __launch_bounds__(64) void reinject_kernel(T* __restrict__ xs, T* __restrict__ vs,
+                                                     const int* __restrict__ lost_list, PushArgs p,
+                                                     Ctl* __restrict__ ctl)
+{
+    const long long cnt = (long long)ctl->cnt[2];
+    const uint64_t n = (uint64_t)ctl->step;
+    const int Npad = p.Npad;
+    for (long long k = blockIdx.x * 64 + threadIdx.x; k < cnt; k += (long long)gridDim.x * 64) {
+        const int i = lost_list[k];
+        double o[6];
+        reinject(p, (uint64_t)i, n, o);
+        xs[i] = (T)o[0]; xs[Npad + i] = (T)o[1]; xs[2 * Npad + i] = (T)o[2];
+        vs[i] = (T)o[3]; vs[Npad + i] = (T)o[4]; vs[2 * Npad + i] = (T)o[5];
     }
 }
 
@@ -477,6 +514,7 @@ __global__ __launch_bounds__(64) void finalize_kernel(FinalArgs f, DustSet ds,
         ctl->last_coll = (long long)ctl->cnt[1];
         ctl->cnt[0] = 0ull;
         ctl->cnt[1] = 0ull;
+        ctl->cnt[2] = 0ull;
         if (n >= f.n_discard) ctl->nrec += 1;
         ctl->step = n + 1;
     }

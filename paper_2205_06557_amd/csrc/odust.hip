@@ -6,10 +6,11 @@
 //             (FP64 mode); Npad = N rounded up to the pair tile, padding slots
 //             parked at a far-away sentinel;
 //   ev        [Npad] per-ion event byte of the last step;
+//   lost      [Npad] indices of the ions the last push removed;
 //   ctl       small control block (charges, int64 fixed-point accumulators,
 //             last-step record, running sums, step counter, status word).
-// All per-step state stays on the device; a step is three launches (pair
-// forces, push, finalize) and needs no host synchronisation.
+// All per-step state stays on the device; a step is four launches (pair
+// forces, push, reinjection, finalize) and needs no host synchronisation.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -33,6 +34,7 @@ constexpr double kPI = 3.14159265358979323846;
 constexpr int kPairBlock = 256;
 constexpr int kPairTile = 256;
 constexpr int kPad = 256;
+constexpr int kReinjGrid = 128;
 
 thread_local std::string g_err;
 
@@ -89,11 +91,12 @@ struct od_system {
     void* v = nullptr;
     void* a = nullptr;
     uint8_t* ev = nullptr;
+    int* lost = nullptr;
     odk::Ctl* ctl = nullptr;
     // timing
     bool timing = false;
     std::vector<hipEvent_t> evpool;
-    std::vector<std::pair<int, int>> marks[3];   // (start idx, stop idx) per class
+    std::vector<std::pair<int, int>> marks[4];   // (start idx, stop idx) per class
     size_t evnext = 0;
 };
 
@@ -259,7 +262,7 @@ od_status launch_step(od_system* s)
 {
     const int gp = (int)(s->Npad / kPairBlock);
     const int gq = (int)((s->N + 255) / 256);
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 4; ++k) {
         int e0 = -1, e1 = -1;
         if (s->timing) {
             e0 = (int)s->evnext;
@@ -277,10 +280,19 @@ od_status launch_step(od_system* s)
         } else if (k == 1) {
             if (s->prec == OD_PREC_FP32)
                 odk::push_kernel<float><<<gq, 256, 0, s->stream>>>(
-                    (float*)s->x, (float*)s->v, (const float*)s->a, s->ev, s->pu, s->ds, s->ctl);
+                    (float*)s->x, (float*)s->v, (const float*)s->a, s->ev, s->lost, s->pu, s->ds,
+                    s->ctl);
             else
                 odk::push_kernel<double><<<gq, 256, 0, s->stream>>>(
-                    (double*)s->x, (double*)s->v, (const double*)s->a, s->ev, s->pu, s->ds, s->ctl);
+                    (double*)s->x, (double*)s->v, (const double*)s->a, s->ev, s->lost, s->pu, s->ds,
+                    s->ctl);
+        } else if (k == 2) {
+            if (s->prec == OD_PREC_FP32)
+                odk::reinject_kernel<float><<<kReinjGrid, 64, 0, s->stream>>>(
+                    (float*)s->x, (float*)s->v, s->lost, s->pu, s->ctl);
+            else
+                odk::reinject_kernel<double><<<kReinjGrid, 64, 0, s->stream>>>(
+                    (double*)s->x, (double*)s->v, s->lost, s->pu, s->ctl);
         } else {
             odk::finalize_kernel<<<1, 64, 0, s->stream>>>(s->fa, s->ds, s->ctl);
         }
@@ -345,8 +357,9 @@ od_status od_init_system(const od_plasma* plasma, const od_sim* sim, const od_du
     s->v = dev_alloc(s, vec);
     s->a = dev_alloc(s, vec);
     s->ev = (uint8_t*)dev_alloc(s, (size_t)s->Npad);
+    s->lost = (int*)dev_alloc(s, (size_t)s->Npad * sizeof(int));
     s->ctl = (odk::Ctl*)dev_alloc(s, sizeof(odk::Ctl));
-    if (!s->x || !s->v || !s->a || !s->ev || !s->ctl) {
+    if (!s->x || !s->v || !s->a || !s->ev || !s->lost || !s->ctl) {
         od_destroy(s);
         return fail(OD_ENOMEM, "device allocation of %zu bytes failed", 3 * vec);
     }
@@ -435,6 +448,7 @@ void od_destroy(od_system* s)
     dev_free(s, s->v);
     dev_free(s, s->a);
     dev_free(s, s->ev);
+    dev_free(s, s->lost);
     dev_free(s, s->ctl);
     for (hipEvent_t e : s->evpool) (void)hipEventDestroy(e);
     delete s;
@@ -582,7 +596,7 @@ od_status od_get_kernel_times(od_system* s, double* ms, int64_t* launches)
 {
     if (!s) return fail(OD_EINVAL, "null system");
     HIPCHK(hipStreamSynchronize(s->stream));
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 4; ++k) {
         double tot = 0.0;
         for (auto& m : s->marks[k]) {
             float t = 0.0f;
