@@ -191,6 +191,67 @@ od_status od_rng_block(uint64_t seed, uint64_t system, const uint64_t* ctr_host,
 od_status od_set_timing(od_system* sys, int32_t enable);
 od_status od_get_kernel_times(od_system* sys, double* ms_host, int64_t* launches_host);
 
+/* ---- batches of independent systems ------------------------------------ */
+
+/* Many independent dust systems (each one the model above, with its own
+ * parameters, grains and N) advanced together on one stream: one launch per
+ * step phase for all systems, the pair forces as a cost-ordered work list
+ * pulled by a persistent grid, optionally captured as a HIP graph of several
+ * steps.  Results of a system equal those of the same system run alone
+ * bit for bit when its pair sum is not split (see od_batch_set_config).
+ * FP32 only (sim[s].precision must be OD_PREC_FP32).
+ *   plasma_host[n_systems], sim_host[n_systems]: per-system parameters;
+ *   dust_host: all grains, system after system; n_dust_host[n_systems];
+ *   hip_stream: NULL creates a private non-blocking stream (graph capture
+ *   cannot use the null stream).
+ * Errors as od_init_system, prefixed with the system index. */
+typedef struct od_batch od_batch;
+od_status od_init_batch(const od_plasma* plasma_host, const od_sim* sim_host, const od_dust* dust_host,
+                        const int32_t* n_dust_host, int32_t n_systems, void* hip_stream,
+                        const od_allocator* allocator, od_batch** out);
+void od_destroy_batch(od_batch* b);
+
+/* Work decomposition of the pair forces.  persistent: a grid of
+ * (CUs x resident blocks) pulls work items from an atomic queue (else one
+ * block per item).  Systems with N <= split_max_n have their source range cut
+ * into jsplit (1..4) parts whose partial accelerations are added, in order,
+ * by the push (changes rounding, not the method).  Drops a captured graph. */
+od_status od_batch_set_config(od_batch* b, int32_t persistent, int32_t jsplit, int64_t split_max_n);
+od_status od_batch_get_config(od_batch* b, int32_t* persistent, int32_t* jsplit, int64_t* split_max_n,
+                              int32_t* n_items);
+
+/* Times the pair phase for each candidate configuration (persistent or not;
+ * jsplit 1, 2, 4; split_max_n 2^15, 2^16), keeps the fastest, and returns its
+ * time in *best_ms.  With cache_path (a text file of one JSON object per
+ * line, keyed by GPU architecture, CU count and the histogram of log2 N of
+ * the systems) a cached choice is reused and a new one appended.  The
+ * systems' state is unchanged. */
+od_status od_batch_autotune(od_batch* b, const char* cache_path, double* best_ms);
+
+/* Capture steps_per_graph (0..1000; 0: no graph) steps as one HIP graph that
+ * od_step_batch replays; the remainder of a step count runs eagerly. */
+od_status od_batch_set_graph(od_batch* b, int32_t steps_per_graph);
+od_status od_step_batch(od_batch* b, int64_t n_steps);
+od_status od_batch_sync(od_batch* b);
+
+/* Per-system access, as the single-system calls (x/v/a float [3][N]):
+ * sizes out_host[4] = {N, n_dust, pair splits, padded N}. */
+od_status od_batch_get_sizes(od_batch* b, int32_t system, int64_t* out_host);
+od_status od_batch_get_dust_charges(od_batch* b, int32_t system, double* q_now_host, double* q_avg_host);
+od_status od_batch_get_dust_forces(od_batch* b, int32_t system, int32_t which, double* f_host);
+od_status od_batch_get_state(od_batch* b, int32_t system, float* x_host, float* v_host, double* q_host,
+                             int64_t* step);
+od_status od_batch_set_state(od_batch* b, int32_t system, const float* x_host, const float* v_host,
+                             const double* q_host, int64_t step);
+od_status od_batch_get_accelerations(od_batch* b, int32_t system, float* a_host);
+od_status od_batch_get_step_events(od_batch* b, int32_t system, uint8_t* ev_host, int64_t* n_abs_host,
+                                   int64_t* n_exit, int64_t* n_coll);
+
+/* Timing as od_set_timing; classes {0 pair, 1 push, 2 reinjection,
+ * 3 finalize, 4 graph replay}: ms_host[5], launches_host[5]. */
+od_status od_batch_set_timing(od_batch* b, int32_t enable);
+od_status od_batch_get_kernel_times(od_batch* b, double* ms_host, int64_t* launches_host);
+
 #ifdef __cplusplus
 }
 #endif

@@ -244,3 +244,201 @@ class System:
         n = np.zeros(len(KERNEL_CLASSES), dtype=np.int64)
         _check(lib().od_get_kernel_times(self._h, _ptr(ms), _ptr(n, C.c_int64)))
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_CLASSES)}
+
+
+_batch_sigs = False
+
+
+def _batch_lib():
+    global _batch_sigs
+    L = lib()
+    if not _batch_sigs:
+        vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        dp, i64p = C.POINTER(C.c_double), C.POINTER(C.c_int64)
+        L.od_init_batch.argtypes = [C.POINTER(Plasma), C.POINTER(Sim), C.POINTER(Dust),
+                                    C.POINTER(C.c_int32), i32, vp, C.POINTER(Allocator), C.POINTER(vp)]
+        L.od_destroy_batch.argtypes = [vp]
+        L.od_destroy_batch.restype = None
+        L.od_batch_set_config.argtypes = [vp, i32, i32, i64]
+        L.od_batch_get_config.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), i64p,
+                                          C.POINTER(C.c_int32)]
+        L.od_batch_autotune.argtypes = [vp, C.c_char_p, dp]
+        L.od_batch_set_graph.argtypes = [vp, i32]
+        L.od_step_batch.argtypes = [vp, i64]
+        L.od_batch_sync.argtypes = [vp]
+        L.od_batch_get_sizes.argtypes = [vp, i32, i64p]
+        L.od_batch_get_dust_charges.argtypes = [vp, i32, dp, dp]
+        L.od_batch_get_dust_forces.argtypes = [vp, i32, i32, dp]
+        L.od_batch_get_state.argtypes = [vp, i32, vp, vp, dp, i64p]
+        L.od_batch_set_state.argtypes = [vp, i32, vp, vp, dp, i64]
+        L.od_batch_get_accelerations.argtypes = [vp, i32, vp]
+        L.od_batch_get_step_events.argtypes = [vp, i32, C.POINTER(C.c_uint8), i64p, i64p, i64p]
+        L.od_batch_set_timing.argtypes = [vp, i32]
+        L.od_batch_get_kernel_times.argtypes = [vp, dp, i64p]
+        for name in ("od_init_batch", "od_batch_set_config", "od_batch_get_config", "od_batch_autotune",
+                     "od_batch_set_graph", "od_step_batch", "od_batch_sync", "od_batch_get_sizes",
+                     "od_batch_get_dust_charges", "od_batch_get_dust_forces", "od_batch_get_state",
+                     "od_batch_set_state", "od_batch_get_accelerations", "od_batch_get_step_events",
+                     "od_batch_set_timing", "od_batch_get_kernel_times"):
+            getattr(L, name).restype = C.c_int
+        _batch_sigs = True
+    return L
+
+
+BATCH_TIME_CLASSES = ("pair", "push", "reinject", "finalize", "graph")
+
+
+class Batch:
+    """Independent dust systems (a list of workloads.Workload) advanced
+    together.  stream=None lets the library create its own stream."""
+
+    def __init__(self, workloads, stream=None, torch_memory: bool = False):
+        L = _batch_lib()
+        ws = list(workloads)
+        self.ws = ws
+        n = len(ws)
+        pls = (Plasma * n)(*[Plasma(w.Te, w.Ti, w.n_inf, w.m_i, w.mach, w.nu_in, w.E_ext) for w in ws])
+        sims = (Sim * n)(*[Sim(w.R, w.H, w.dt, int(w.n_ions), int(w.n_discard), int(w.seed),
+                               int(w.system_id), int(w.charge_mode), PREC_FP32, int(w.flags), 0)
+                           for w in ws])
+        dl = [Dust(*d) for w in ws for d in w.dust]
+        dust = (Dust * max(len(dl), 1))(*dl)
+        nd = (C.c_int32 * n)(*[len(w.dust) for w in ws])
+        self._alloc = TorchAllocator() if torch_memory else None
+        h = C.c_void_p()
+        _check(L.od_init_batch(pls, sims, dust, nd, n, stream,
+                               C.byref(self._alloc.struct) if self._alloc else None, C.byref(h)))
+        self._h = h
+        self.n = n
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _batch_lib().od_destroy_batch(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_config(self, persistent: bool = True, jsplit: int = 1, split_max_n: int = 0):
+        _check(_batch_lib().od_batch_set_config(self._h, 1 if persistent else 0, int(jsplit),
+                                                int(split_max_n)))
+
+    def config(self):
+        p, j, n = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+        t = C.c_int64(0)
+        _check(_batch_lib().od_batch_get_config(self._h, C.byref(p), C.byref(j), C.byref(t), C.byref(n)))
+        return dict(persistent=p.value, jsplit=j.value, split_max_n=t.value, n_items=n.value)
+
+    def autotune(self, cache_path: Optional[str] = None) -> float:
+        ms = C.c_double(0)
+        _check(_batch_lib().od_batch_autotune(self._h, cache_path.encode() if cache_path else None,
+                                              C.byref(ms)))
+        return ms.value
+
+    def set_graph(self, steps: int):
+        _check(_batch_lib().od_batch_set_graph(self._h, int(steps)))
+
+    def step(self, n: int = 1):
+        _check(_batch_lib().od_step_batch(self._h, int(n)))
+
+    def sync(self):
+        _check(_batch_lib().od_batch_sync(self._h))
+
+    def sizes(self, s: int):
+        o = np.zeros(4, dtype=np.int64)
+        _check(_batch_lib().od_batch_get_sizes(self._h, s, _ptr(o, C.c_int64)))
+        return dict(N=int(o[0]), n_dust=int(o[1]), nsplit=int(o[2]), Npad=int(o[3]))
+
+    def charges(self, s: int):
+        nd = max(len(self.ws[s].dust), 1)
+        q, qa = np.zeros(nd), np.zeros(nd)
+        _check(_batch_lib().od_batch_get_dust_charges(self._h, s, _ptr(q), _ptr(qa)))
+        return q[: len(self.ws[s].dust)], qa[: len(self.ws[s].dust)]
+
+    def forces(self, s: int, which: int = 0):
+        nd = len(self.ws[s].dust)
+        f = np.zeros((max(nd, 1), 4, 3))
+        _check(_batch_lib().od_batch_get_dust_forces(self._h, s, which, _ptr(f)))
+        return f[:nd]
+
+    def get_state(self, s: int):
+        N = int(self.ws[s].n_ions)
+        x = np.zeros((3, N), dtype=np.float32)
+        v = np.zeros((3, N), dtype=np.float32)
+        q = np.zeros(max(len(self.ws[s].dust), 1))
+        st = C.c_int64(0)
+        _check(_batch_lib().od_batch_get_state(self._h, s, x.ctypes.data, v.ctypes.data, _ptr(q),
+                                               C.byref(st)))
+        return x, v, q[: len(self.ws[s].dust)], st.value
+
+    def set_state(self, s: int, x=None, v=None, q=None, step: int = 0):
+        N = int(self.ws[s].n_ions)
+        xs = None if x is None else np.ascontiguousarray(x, dtype=np.float32).reshape(3, N)
+        vs = None if v is None else np.ascontiguousarray(v, dtype=np.float32).reshape(3, N)
+        qs = None if q is None else np.ascontiguousarray(q, dtype=np.float64)
+        _check(_batch_lib().od_batch_set_state(self._h, s, None if xs is None else xs.ctypes.data,
+                                               None if vs is None else vs.ctypes.data, _ptr(qs),
+                                               int(step)))
+
+    def accelerations(self, s: int):
+        a = np.zeros((3, int(self.ws[s].n_ions)), dtype=np.float32)
+        _check(_batch_lib().od_batch_get_accelerations(self._h, s, a.ctypes.data))
+        return a
+
+    def events(self, s: int):
+        N = int(self.ws[s].n_ions)
+        ev = np.zeros(N, dtype=np.uint8)
+        nabs = np.zeros(max(len(self.ws[s].dust), 1), dtype=np.int64)
+        ne, nc = C.c_int64(0), C.c_int64(0)
+        _check(_batch_lib().od_batch_get_step_events(self._h, s, _ptr(ev, C.c_uint8),
+                                                     _ptr(nabs, C.c_int64), C.byref(ne), C.byref(nc)))
+        return ev, nabs[: len(self.ws[s].dust)], ne.value, nc.value
+
+    def set_timing(self, enable: bool):
+        _check(_batch_lib().od_batch_set_timing(self._h, 1 if enable else 0))
+
+    def kernel_times(self):
+        ms = np.zeros(5)
+        n = np.zeros(5, dtype=np.int64)
+        _check(_batch_lib().od_batch_get_kernel_times(self._h, _ptr(ms), _ptr(n, C.c_int64)))
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(BATCH_TIME_CLASSES)}
+
+
+class BatchMember:
+    """Adapter exposing one system of a Batch with the System interface used
+    by the shadowed-step parity helper."""
+
+    def __init__(self, batch: Batch, s: int):
+        self.b, self.s = batch, s
+        self.N = int(batch.ws[s].n_ions)
+        self.precision = PREC_FP32
+
+    def get_state(self):
+        return self.b.get_state(self.s)
+
+    def set_state(self, x=None, v=None, q=None, step: int = 0):
+        self.b.set_state(self.s, x, v, q, step)
+
+    def step(self, n: int = 1):
+        self.b.step(n)
+
+    def sync(self):
+        self.b.sync()
+
+    def accelerations(self):
+        return self.b.accelerations(self.s)
+
+    def events(self):
+        return self.b.events(self.s)
+
+    def forces(self, which: int = 0):
+        return self.b.forces(self.s, which)
+
+    def charges(self):
+        return self.b.charges(self.s)

@@ -62,29 +62,31 @@ struct FinalArgs {
 };
 
 // ---------------------------------------------------------------------------
-// Forces, FP32 tiles.  One ion per thread; the block stages TJ source ions at
-// a time in LDS as float4 and every lane reads them with a broadcast load.
-// Inner sums run in FP32 over one tile and are added to FP64 totals per tile.
+// Forces, FP32 tiles.  One block's share of the pair sum: target ions
+// [i0, i0 + BLOCK) of one system (planes X/Y/Z, local indices) against the
+// sources [jb, je), one target per lane.  The block stages TJ sources at a
+// time in LDS as float4 and every lane reads them with a broadcast load;
+// sums run in FP32 over a tile and are added to FP64 totals per tile.  The
+// result (times the ion-ion coupling) goes to out planes oX/oY/oZ.  With
+// `epi` set, the grain and drive terms are added and the Eq. (1) sums of the
+// block are reduced and added to the system's fixed-point accumulators.
 template <int BLOCK, int TJ>
-__global__ __launch_bounds__(BLOCK) void pair_forces_f32(const float* __restrict__ xs,
-                                                         float* __restrict__ acc,
-                                                         PairArgs p, DustSet ds,
-                                                         Ctl* __restrict__ ctl)
+__device__ __forceinline__ void pair_block_f32(const float* __restrict__ X,
+                                               const float* __restrict__ Y,
+                                               const float* __restrict__ Z, int i0, int jb,
+                                               int je, const PairArgs& p, const DustSet& ds,
+                                               Ctl* __restrict__ ctl, float* __restrict__ oX,
+                                               float* __restrict__ oY, float* __restrict__ oZ,
+                                               bool epi, float4* tile,
+                                               double (*red)[kMaxDust][3])
 {
-    __shared__ float4 tile[TJ];
-    __shared__ double red[BLOCK / 64][kMaxDust][3];
-    const int Npad = p.Npad;
-    const float* X = xs;
-    const float* Y = xs + Npad;
-    const float* Z = xs + 2 * Npad;
-    const int i0 = blockIdx.x * BLOCK;
     const int i = i0 + threadIdx.x;
     const float xi = X[i], yi = Y[i], zi = Z[i];
     double sx = 0.0, sy = 0.0, sz = 0.0;
     const float kNegLog2e = -1.4426950408889634f;
 
     if (p.ion_ion) {
-        for (int j0 = 0; j0 < Npad; j0 += TJ) {
+        for (int j0 = jb; j0 < je; j0 += TJ) {
             __syncthreads();
             for (int t = threadIdx.x; t < TJ; t += BLOCK)
                 tile[t] = make_float4(X[j0 + t], Y[j0 + t], Z[j0 + t], 0.0f);
@@ -129,39 +131,58 @@ __global__ __launch_bounds__(BLOCK) void pair_forces_f32(const float* __restrict
         }
     }
 
-    // Epilogue: grain terms in FP64 (N_d per ion).
     const bool live = i < p.N;
-    const double xd = xi, yd = yi, zd = zi;
-    double gx = p.Cd * sx, gy = p.Cd * sy, gz = p.Cd * sz + p.Ez;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int d = 0; d < ds.nd; ++d) {
-        const double rx = xd - ds.pos[d][0], ry = yd - ds.pos[d][1], rz = zd - ds.pos[d][2];
-        const double r2 = rx * rx + ry * ry + rz * rz;
-        const double r = sqrt(r2);
-        const double ir3 = 1.0 / (r2 * r);
-        const double kq = p.Kq * ctl->Q[d] * ir3;               // bare Coulomb on the ion
-        gx += kq * rx; gy += kq * ry; gz += kq * rz;
-        // Eq. (1) summand: (1 + rho) e^-rho / rho^3 (r_d - x_i)
-        double f = live ? -(1.0 + r) * exp(-r) * ir3 : 0.0;
-        double fx = wave_sum(f * rx), fy = wave_sum(f * ry), fz = wave_sum(f * rz);
-        if (lane == 0) {
-            red[wv][d][0] = fx;
-            red[wv][d][1] = fy;
-            red[wv][d][2] = fz;
+    double gx = p.Cd * sx, gy = p.Cd * sy, gz = p.Cd * sz;
+    if (epi) {
+        // grain terms in FP64 (N_d per ion) and the drive
+        const double xd = xi, yd = yi, zd = zi;
+        gz += p.Ez;
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        for (int d = 0; d < ds.nd; ++d) {
+            const double rx = xd - ds.pos[d][0], ry = yd - ds.pos[d][1], rz = zd - ds.pos[d][2];
+            const double r2 = rx * rx + ry * ry + rz * rz;
+            const double r = sqrt(r2);
+            const double ir3 = 1.0 / (r2 * r);
+            const double kq = p.Kq * ctl->Q[d] * ir3;               // bare Coulomb on the ion
+            gx += kq * rx; gy += kq * ry; gz += kq * rz;
+            // Eq. (1) summand: (1 + rho) e^-rho / rho^3 (r_d - x_i)
+            double f = live ? -(1.0 + r) * exp(-r) * ir3 : 0.0;
+            double fx = wave_sum(f * rx), fy = wave_sum(f * ry), fz = wave_sum(f * rz);
+            if (lane == 0) {
+                red[wv][d][0] = fx;
+                red[wv][d][1] = fy;
+                red[wv][d][2] = fz;
+            }
         }
     }
     if (live) {
-        acc[i] = (float)gx;
-        acc[Npad + i] = (float)gy;
-        acc[2 * Npad + i] = (float)gz;
+        oX[i] = (float)gx;
+        oY[i] = (float)gy;
+        oZ[i] = (float)gz;
+    }
+    if (epi) {
+        __syncthreads();
+        for (int t = threadIdx.x; t < ds.nd * 3; t += BLOCK) {
+            const int d = t / 3, c = t % 3;
+            double s = 0.0;
+            for (int w = 0; w < BLOCK / 64; ++w) s += red[w][d][c];
+            atomicAdd(&ctl->acc[d][c], to_fixed(s, kForceScale, &ctl->status));
+        }
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < ds.nd * 3; t += BLOCK) {
-        const int d = t / 3, c = t % 3;
-        double s = 0.0;
-        for (int w = 0; w < BLOCK / 64; ++w) s += red[w][d][c];
-        atomicAdd(&ctl->acc[d][c], to_fixed(s, kForceScale, &ctl->status));
-    }
+}
+
+template <int BLOCK, int TJ>
+__global__ __launch_bounds__(BLOCK) void pair_forces_f32(const float* __restrict__ xs,
+                                                         float* __restrict__ acc,
+                                                         PairArgs p, DustSet ds,
+                                                         Ctl* __restrict__ ctl)
+{
+    __shared__ float4 tile[TJ];
+    __shared__ double red[BLOCK / 64][kMaxDust][3];
+    const int Npad = p.Npad;
+    pair_block_f32<BLOCK, TJ>(xs, xs + Npad, xs + 2 * Npad, blockIdx.x * BLOCK, 0, Npad, p, ds, ctl,
+                              acc, acc + Npad, acc + 2 * Npad, true, tile, red);
 }
 
 // Forces, FP64 throughout (precision mode OD_PREC_FP64).
@@ -310,7 +331,124 @@ __device__ void reinject(const PushArgs& p, uint64_t ion, uint64_t n, double o[6
 }
 
 // ---------------------------------------------------------------------------
-// Push: one ion per thread.
+// Push of one ion: kick with the acceleration (the sum of `nsplit` partial
+// planes `sstride` apart), charge exchange, drift, absorption test against
+// every grain along the drift segment, exit test.  Planes use the system's
+// local ion index.  Absorbed ions add to the grain's count and momentum.
+template <typename T>
+__device__ __forceinline__ void push_ion(T* __restrict__ X, T* __restrict__ Y, T* __restrict__ Z,
+                                         T* __restrict__ VX, T* __restrict__ VY,
+                                         T* __restrict__ VZ, const T* __restrict__ AX,
+                                         const T* __restrict__ AY, const T* __restrict__ AZ,
+                                         long long sstride, int nsplit, int i, uint64_t n,
+                                         const PushArgs& p, const DustSet& ds,
+                                         Ctl* __restrict__ ctl, uint8_t& code, bool& coll,
+                                         bool& lost)
+{
+    const T dt = (T)p.dt;
+    T ax = AX[i], ay = AY[i], az = AZ[i];
+    for (int k = 1; k < nsplit; ++k) {
+        ax += AX[i + k * sstride];
+        ay += AY[i + k * sstride];
+        az += AZ[i + k * sstride];
+    }
+    const T x0 = X[i], x1 = Y[i], x2 = Z[i];
+    T v0 = VX[i] + dt * ax;
+    T v1 = VY[i] + dt * ay;
+    T v2 = VZ[i] + dt * az;
+    if (p.Tc != 0) {
+        const U64x4 r = philox((uint64_t)i, n, kColl, 0, p.k0, p.k1);
+        if (r.w[0] < p.Tc) {
+            const U64x4 g = philox((uint64_t)i, n, kColl, 1, p.k0, p.k1);
+            double g1, g2, g3, g4;
+            gauss2(unit(g.w[0]), unit(g.w[1]), g1, g2);
+            gauss2(unit(g.w[2]), unit(g.w[3]), g3, g4);
+            v0 = (T)(p.sig * g1);
+            v1 = (T)(p.sig * g2);
+            v2 = (T)(p.sig * g3);
+            coll = true;
+        }
+    }
+    const T y0 = x0 + dt * v0, y1 = x1 + dt * v1, y2 = x2 + dt * v2;
+    // Absorption: does the drift segment x -> y meet a grain?  FP64 on
+    // the stored values; the earliest entry wins, ties to the lower index.
+    int hit = -1;
+    double tbest = 2.0;
+    const double D0 = (double)y0 - (double)x0, D1 = (double)y1 - (double)x1,
+                 D2 = (double)y2 - (double)x2;
+    const double DD = D0 * D0 + D1 * D1 + D2 * D2;
+    for (int d = 0; d < ds.nd; ++d) {
+        const double s0 = (double)x0 - ds.pos[d][0], s1 = (double)x1 - ds.pos[d][1],
+                     s2 = (double)x2 - ds.pos[d][2];
+        const double a2 = ds.rad2[d];
+        const double ss = s0 * s0 + s1 * s1 + s2 * s2;
+        const double sD = s0 * D0 + s1 * D1 + s2 * D2;
+        // squared closest approach of the segment, without a division:
+        // at the start if moving away, at the end if the foot of the
+        // perpendicular lies beyond it, else ss - sD^2/DD (scaled by DD)
+        bool in;
+        if (DD == 0.0 || sD >= 0.0) {
+            in = ss <= a2;
+        } else if (-sD >= DD) {
+            const double e0 = (double)y0 - ds.pos[d][0], e1 = (double)y1 - ds.pos[d][1],
+                         e2 = (double)y2 - ds.pos[d][2];
+            in = e0 * e0 + e1 * e1 + e2 * e2 <= a2;
+        } else {
+            in = ss * DD - sD * sD <= a2 * DD;
+        }
+        if (in) {   // rare: entry parameter of the first crossing
+            double th = 0.0;
+            if (DD > 0.0) {
+                const double disc = fmax(sD * sD - DD * (ss - a2), 0.0);
+                th = fmax((-sD - sqrt(disc)) / DD, 0.0);
+            }
+            if (th < tbest) {
+                tbest = th;
+                hit = d;
+            }
+        }
+    }
+    if (hit >= 0) {
+        code = (uint8_t)(kEvAbsBase + hit);
+        atomicAdd(&ctl->acc[hit][3], 1ull);
+        atomicAdd(&ctl->acc[hit][4], to_fixed((double)v0, kMomScale, &ctl->status));
+        atomicAdd(&ctl->acc[hit][5], to_fixed((double)v1, kMomScale, &ctl->status));
+        atomicAdd(&ctl->acc[hit][6], to_fixed((double)v2, kMomScale, &ctl->status));
+        lost = true;
+    } else {
+        const double rr = (double)y0 * (double)y0 + (double)y1 * (double)y1;
+        if (rr > p.R * p.R || fabs((double)y2) > 0.5 * p.H) {
+            code = kEvExit;
+            lost = true;
+        }
+    }
+    // lost ions are overwritten by the reinjection kernel
+    X[i] = y0; Y[i] = y1; Z[i] = y2;
+    VX[i] = v0; VY[i] = v1; VZ[i] = v2;
+}
+
+// Wave totals of exits and collisions into the system's counters, and a slot
+// in a list (of length *list_len) for every lane with `lost` set.  All lanes
+// of the wave must call it.  Returns the lane's slot (valid if `lost`).
+__device__ __forceinline__ unsigned long long wave_tally(Ctl* __restrict__ ctl, uint8_t code,
+                                                         bool coll, bool lost,
+                                                         unsigned long long* list_len)
+{
+    const unsigned long long ex = __ballot(code == kEvExit);
+    const unsigned long long cl = __ballot(coll);
+    const unsigned long long ls = __ballot(lost);
+    const int lane = threadIdx.x & 63;
+    unsigned long long base = 0;
+    if (lane == 0) {
+        if (ex) atomicAdd(&ctl->cnt[0], (unsigned long long)__popcll(ex));
+        if (cl) atomicAdd(&ctl->cnt[1], (unsigned long long)__popcll(cl));
+        if (ls) base = atomicAdd(list_len, (unsigned long long)__popcll(ls));
+    }
+    base = __shfl(base, 0, 64);
+    return base + __popcll(ls & ((1ull << lane) - 1ull));
+}
+
+// Push of one system: one ion per thread.
 template <typename T>
 __global__ __launch_bounds__(256) void push_kernel(T* __restrict__ xs, T* __restrict__ vs,
                                                    const T* __restrict__ as,
@@ -321,108 +459,32 @@ __global__ __launch_bounds__(256) void push_kernel(T* __restrict__ xs, T* __rest
     const int i = blockIdx.x * 256 + threadIdx.x;
     const int Npad = p.Npad;
     const uint64_t n = (uint64_t)ctl->step;
-    bool coll = false;
-    bool lost = false;
+    bool coll = false, lost = false;
     uint8_t code = kEvNone;
     if (i < p.N) {
-        const T dt = (T)p.dt;
-        T x0 = xs[i], x1 = xs[Npad + i], x2 = xs[2 * Npad + i];
-        T v0 = vs[i] + dt * as[i];
-        T v1 = vs[Npad + i] + dt * as[Npad + i];
-        T v2 = vs[2 * Npad + i] + dt * as[2 * Npad + i];
-        if (p.Tc != 0) {
-            const U64x4 r = philox((uint64_t)i, n, kColl, 0, p.k0, p.k1);
-            if (r.w[0] < p.Tc) {
-                const U64x4 g = philox((uint64_t)i, n, kColl, 1, p.k0, p.k1);
-                double g1, g2, g3, g4;
-                gauss2(unit(g.w[0]), unit(g.w[1]), g1, g2);
-                gauss2(unit(g.w[2]), unit(g.w[3]), g3, g4);
-                v0 = (T)(p.sig * g1);
-                v1 = (T)(p.sig * g2);
-                v2 = (T)(p.sig * g3);
-                coll = true;
-            }
-        }
-        const T y0 = x0 + dt * v0, y1 = x1 + dt * v1, y2 = x2 + dt * v2;
-        // Absorption: does the drift segment x -> y meet a grain?  FP64 on
-        // the stored values; the earliest entry wins, ties to the lower index.
-        int hit = -1;
-        double tbest = 2.0;
-        const double D0 = (double)y0 - (double)x0, D1 = (double)y1 - (double)x1,
-                     D2 = (double)y2 - (double)x2;
-        const double DD = D0 * D0 + D1 * D1 + D2 * D2;
-        for (int d = 0; d < ds.nd; ++d) {
-            const double s0 = (double)x0 - ds.pos[d][0], s1 = (double)x1 - ds.pos[d][1],
-                         s2 = (double)x2 - ds.pos[d][2];
-            const double a2 = ds.rad2[d];
-            const double ss = s0 * s0 + s1 * s1 + s2 * s2;
-            const double sD = s0 * D0 + s1 * D1 + s2 * D2;
-            // squared closest approach of the segment, without a division:
-            // at the start if moving away, at the end if the foot of the
-            // perpendicular lies beyond it, else ss - sD^2/DD (scaled by DD)
-            bool in;
-            if (DD == 0.0 || sD >= 0.0) {
-                in = ss <= a2;
-            } else if (-sD >= DD) {
-                const double e0 = (double)y0 - ds.pos[d][0], e1 = (double)y1 - ds.pos[d][1],
-                             e2 = (double)y2 - ds.pos[d][2];
-                in = e0 * e0 + e1 * e1 + e2 * e2 <= a2;
-            } else {
-                in = ss * DD - sD * sD <= a2 * DD;
-            }
-            if (in) {   // rare: entry parameter of the first crossing
-                double th = 0.0;
-                if (DD > 0.0) {
-                    const double disc = fmax(sD * sD - DD * (ss - a2), 0.0);
-                    th = fmax((-sD - sqrt(disc)) / DD, 0.0);
-                }
-                if (th < tbest) {
-                    tbest = th;
-                    hit = d;
-                }
-            }
-        }
-        if (hit >= 0) {
-            code = (uint8_t)(kEvAbsBase + hit);
-            atomicAdd(&ctl->acc[hit][3], 1ull);
-            atomicAdd(&ctl->acc[hit][4], to_fixed((double)v0, kMomScale, &ctl->status));
-            atomicAdd(&ctl->acc[hit][5], to_fixed((double)v1, kMomScale, &ctl->status));
-            atomicAdd(&ctl->acc[hit][6], to_fixed((double)v2, kMomScale, &ctl->status));
-            lost = true;
-        } else {
-            const double rr = (double)y0 * (double)y0 + (double)y1 * (double)y1;
-            if (rr > p.R * p.R || fabs((double)y2) > 0.5 * p.H) {
-                code = kEvExit;
-                lost = true;
-            }
-        }
-        // lost ions are overwritten by the reinjection kernel
-        xs[i] = y0; xs[Npad + i] = y1; xs[2 * Npad + i] = y2;
-        vs[i] = v0; vs[Npad + i] = v1; vs[2 * Npad + i] = v2;
+        push_ion<T>(xs, xs + Npad, xs + 2 * Npad, vs, vs + Npad, vs + 2 * Npad, as, as + Npad,
+                    as + 2 * Npad, 0, 1, i, n, p, ds, ctl, code, coll, lost);
         ev[i] = code | (coll ? kEvCollBit : 0);
     }
-    // wave totals of exits and collisions; lost ions appended to the list
-    const unsigned long long ex = __ballot(code == kEvExit);
-    const unsigned long long cl = __ballot(coll);
-    const unsigned long long ls = __ballot(lost);
-    const int lane = threadIdx.x & 63;
-    unsigned long long base = 0;
-    if (lane == 0) {
-        if (ex) atomicAdd(&ctl->cnt[0], (unsigned long long)__popcll(ex));
-        if (cl) atomicAdd(&ctl->cnt[1], (unsigned long long)__popcll(cl));
-        if (ls) base = atomicAdd(&ctl->cnt[2], (unsigned long long)__popcll(ls));
-    }
-    if (ls) {
-        base = __shfl(base, 0, 64);
-        if (lost) {
-            const unsigned long long below = ls & ((1ull << lane) - 1ull);
-            lost_list[base + __popcll(below)] = i;
-        }
-    }
+    const unsigned long long slot = wave_tally(ctl, code, coll, lost, &ctl->cnt[2]);
+    if (lost) lost_list[slot] = i;
 }
 
-// Reinjection of the ions the push listed (Appendix B).  A fixed grid walks
-// the list, whose length the push left in the control block.
+// New boundary position and velocity of listed ion i (Appendix B).
+template <typename T>
+__device__ __forceinline__ void reinject_ion(T* __restrict__ X, T* __restrict__ Y,
+                                             T* __restrict__ Z, T* __restrict__ VX,
+                                             T* __restrict__ VY, T* __restrict__ VZ, int i,
+                                             uint64_t n, const PushArgs& p)
+{
+    double o[6];
+    reinject(p, (uint64_t)i, n, o);
+    X[i] = (T)o[0]; Y[i] = (T)o[1]; Z[i] = (T)o[2];
+    VX[i] = (T)o[3]; VY[i] = (T)o[4]; VZ[i] = (T)o[5];
+}
+
+// Reinjection of the ions the push listed.  A fixed grid walks the list,
+// whose length the push left in the control block.
 template <typename T>
 __global__ __launch_bounds__(64) void reinject_kernel(T* __restrict__ xs, T* __restrict__ vs,
                                                      const int* __restrict__ lost_list, PushArgs p,
@@ -431,22 +493,19 @@ __global__ __launch_bounds__(64) void reinject_kernel(T* __restrict__ xs, T* __r
     const long long cnt = (long long)ctl->cnt[2];
     const uint64_t n = (uint64_t)ctl->step;
     const int Npad = p.Npad;
-    for (long long k = blockIdx.x * 64 + threadIdx.x; k < cnt; k += (long long)gridDim.x * 64) {
-        const int i = lost_list[k];
-        double o[6];
-        reinject(p, (uint64_t)i, n, o);
-        xs[i] = (T)o[0]; xs[Npad + i] = (T)o[1]; xs[2 * Npad + i] = (T)o[2];
-        vs[i] = (T)o[3]; vs[Npad + i] = (T)o[4]; vs[2 * Npad + i] = (T)o[5];
-    }
+    for (long long k = blockIdx.x * 64 + threadIdx.x; k < cnt; k += (long long)gridDim.x * 64)
+        reinject_ion<T>(xs, xs + Npad, xs + 2 * Npad, vs, vs + Npad, vs + 2 * Npad, lost_list[k],
+                        n, p);
 }
 
 // ---------------------------------------------------------------------------
-// Finalize: one wave, lane d handles grain d.
-__global__ __launch_bounds__(64) void finalize_kernel(FinalArgs f, DustSet ds,
-                                                      Ctl* __restrict__ ctl)
+// Finalize of one system by one wave (lane d handles grain d): charge update,
+// the four force parts in SI, recording, running sums, counters cleared,
+// step counter advanced.
+__device__ __forceinline__ void finalize_sys(const FinalArgs& f, const DustSet& ds,
+                                             Ctl* __restrict__ ctl, double* Qs)
 {
     const int d = threadIdx.x;
-    __shared__ double Qs[kMaxDust];
     if (d < f.nd) Qs[d] = ctl->Q[d];
     __syncthreads();
     const long long n = ctl->step;
@@ -520,23 +579,27 @@ __global__ __launch_bounds__(64) void finalize_kernel(FinalArgs f, DustSet ds,
     }
 }
 
-// ---------------------------------------------------------------------------
-// Initial state: uniform in the cylinder outside every grain, velocities from
-// N((0,0,u), sig^2).  Padding slots get a far-away sentinel position that
-// contributes exactly zero to every pair sum.
-template <typename T>
-__global__ __launch_bounds__(256) void init_kernel(T* __restrict__ xs, T* __restrict__ vs,
-                                                   T* __restrict__ as, PushArgs p, DustSet ds,
-                                                   Ctl* __restrict__ ctl)
+__global__ __launch_bounds__(64) void finalize_kernel(FinalArgs f, DustSet ds,
+                                                      Ctl* __restrict__ ctl)
 {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    const int Npad = p.Npad;
-    if (i >= Npad) return;
+    __shared__ double Qs[kMaxDust];
+    finalize_sys(f, ds, ctl, Qs);
+}
+
+// ---------------------------------------------------------------------------
+// Initial state of ion i: uniform in the cylinder outside every grain,
+// velocity from N((0,0,u), sig^2).  Padding slots get a far-away sentinel
+// position that contributes exactly zero to every pair sum.
+template <typename T>
+__device__ __forceinline__ void init_ion(T* __restrict__ X, T* __restrict__ Y, T* __restrict__ Z,
+                                         T* __restrict__ VX, T* __restrict__ VY,
+                                         T* __restrict__ VZ, int i, const PushArgs& p,
+                                         const DustSet& ds, Ctl* __restrict__ ctl)
+{
     if (i >= p.N) {
         const T far = (T)1.0e18;
-        xs[i] = far; xs[Npad + i] = far; xs[2 * Npad + i] = far;
-        vs[i] = 0; vs[Npad + i] = 0; vs[2 * Npad + i] = 0;
-        as[i] = 0; as[Npad + i] = 0; as[2 * Npad + i] = 0;
+        X[i] = far; Y[i] = far; Z[i] = far;
+        VX[i] = 0; VY[i] = 0; VZ[i] = 0;
         return;
     }
     double px = 0.0, py = 0.0, pz = 0.0;
@@ -560,8 +623,19 @@ __global__ __launch_bounds__(256) void init_kernel(T* __restrict__ xs, T* __rest
     double g1, g2, g3, g4;
     gauss2(unit(g.w[0]), unit(g.w[1]), g1, g2);
     gauss2(unit(g.w[2]), unit(g.w[3]), g3, g4);
-    xs[i] = (T)px; xs[Npad + i] = (T)py; xs[2 * Npad + i] = (T)pz;
-    vs[i] = (T)(p.sig * g1); vs[Npad + i] = (T)(p.sig * g2); vs[2 * Npad + i] = (T)(p.ubar + p.sig * g3);
+    X[i] = (T)px; Y[i] = (T)py; Z[i] = (T)pz;
+    VX[i] = (T)(p.sig * g1); VY[i] = (T)(p.sig * g2); VZ[i] = (T)(p.ubar + p.sig * g3);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void init_kernel(T* __restrict__ xs, T* __restrict__ vs,
+                                                   T* __restrict__ as, PushArgs p, DustSet ds,
+                                                   Ctl* __restrict__ ctl)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int Npad = p.Npad;
+    if (i >= Npad) return;
+    init_ion<T>(xs, xs + Npad, xs + 2 * Npad, vs, vs + Npad, vs + 2 * Npad, i, p, ds, ctl);
     as[i] = 0; as[Npad + i] = 0; as[2 * Npad + i] = 0;
 }
 

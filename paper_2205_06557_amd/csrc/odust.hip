@@ -67,6 +67,14 @@ uint64_t prob_to_threshold(double p)
 double normal_cdf(double t) { return 0.5 * std::erfc(-t / std::sqrt(2.0)); }
 double normal_pdf(double t) { return std::exp(-0.5 * t * t) / std::sqrt(2.0 * kPI); }
 
+struct SysConsts {
+    double lam = 0, wpi = 0, cs = 0;
+    odk::DustSet ds{};
+    odk::PairArgs pa{};
+    odk::PushArgs pu{};
+    odk::FinalArgs fa{};
+};
+
 }  // namespace
 
 struct od_system {
@@ -156,16 +164,15 @@ od_status check_params(const od_plasma* pl, const od_sim* sim, const od_dust* du
 }
 
 // SI -> dimensionless constants of every kernel.
-void derive(od_system* s)
+void derive_consts(const od_plasma& P, const od_sim& S, const od_dust* dust, int nd, int64_t N,
+                   int64_t Npad, SysConsts& c)
 {
-    const od_plasma& P = s->pl;
-    const od_sim& S = s->sim;
     const double lam = std::sqrt(kEPS0 * kKB * P.T_e / (P.n_inf * kQE * kQE));
     const double wpi = std::sqrt(P.n_inf * kQE * kQE / (kEPS0 * P.m_i));
     const double cs = lam * wpi;
-    s->lam = lam;
-    s->wpi = wpi;
-    s->cs = cs;
+    c.lam = lam;
+    c.wpi = wpi;
+    c.cs = cs;
     const double sig = std::sqrt(P.T_i / P.T_e);
     const double ubar = P.mach;
     const double R = S.R / lam, H = S.H / lam, dt = S.dt * wpi, nu = P.nu_in / wpi;
@@ -182,20 +189,20 @@ void derive(od_system* s)
     }
     const double Pc = -std::expm1(-nu * dt);
 
-    odk::DustSet& ds = s->ds;
-    ds.nd = s->nd;
-    for (int d = 0; d < s->nd; ++d) {
-        ds.pos[d][0] = s->dust[d].x / lam;
-        ds.pos[d][1] = s->dust[d].y / lam;
-        ds.pos[d][2] = s->dust[d].z / lam;
-        const double a = s->dust[d].radius / lam;
+    odk::DustSet& ds = c.ds;
+    ds.nd = nd;
+    for (int d = 0; d < nd; ++d) {
+        ds.pos[d][0] = dust[d].x / lam;
+        ds.pos[d][1] = dust[d].y / lam;
+        ds.pos[d][2] = dust[d].z / lam;
+        const double a = dust[d].radius / lam;
         ds.rad2[d] = a * a;
     }
 
-    odk::PairArgs& pa = s->pa;
-    pa.N = (int)s->N;
-    pa.Npad = (int)s->Npad;
-    pa.nd = s->nd;
+    odk::PairArgs& pa = c.pa;
+    pa.N = (int)N;
+    pa.Npad = (int)Npad;
+    pa.nd = nd;
     pa.ion_ion = (S.flags & OD_FLAG_NO_ION_ION) ? 0 : 1;
     pa.Cd = Vt / (4.0 * kPI * (double)S.n_ions);
     pa.C = (float)pa.Cd;
@@ -209,10 +216,10 @@ void derive(od_system* s)
     const double Js = 2.0 * kPI * R * H * sig / std::sqrt(2.0 * kPI);
     const double J = Jb + Jt + Js;
 
-    odk::PushArgs& pu = s->pu;
-    pu.N = (int)s->N;
-    pu.Npad = (int)s->Npad;
-    pu.nd = s->nd;
+    odk::PushArgs& pu = c.pu;
+    pu.N = (int)N;
+    pu.Npad = (int)Npad;
+    pu.nd = nd;
     pu.flags = S.flags;
     pu.dt = dt;
     pu.sig = sig;
@@ -225,16 +232,16 @@ void derive(od_system* s)
     pu.Tb = prob_to_threshold(Jb / J);
     pu.Tbt = prob_to_threshold((Jb + Jt) / J);
 
-    odk::FinalArgs& fa = s->fa;
-    fa.nd = s->nd;
+    odk::FinalArgs& fa = c.fa;
+    fa.nd = nd;
     fa.mode = S.charge_mode;
     fa.n_discard = S.n_discard;
     fa.dt = dt;
     fa.w = w;
     const double ve = std::sqrt(8.0 * kKB * P.T_e / (kPI * kME));
     const double vt = std::sqrt(2.0 * kKB * P.T_i / P.m_i);
-    for (int d = 0; d < s->nd; ++d) {
-        const double a = s->dust[d].radius;
+    for (int d = 0; d < nd; ++d) {
+        const double a = dust[d].radius;
         fa.Ie0[d] = kPI * a * a * P.n_inf * ve / wpi;
         fa.Ii0[d] = kPI * a * a * P.n_inf * vt / wpi;
         fa.psi[d] = kQE * kQE / (4.0 * kPI * kEPS0 * a * kKB * P.T_e);
@@ -246,6 +253,19 @@ void derive(od_system* s)
     fa.c_dd = k_e2;
     fa.c_coll = w * P.m_i * cs / S.dt;
     fa.c_ext = kQE * E_si;
+}
+
+void derive(od_system* s)
+{
+    SysConsts c;
+    derive_consts(s->pl, s->sim, s->dust, s->nd, s->N, s->Npad, c);
+    s->lam = c.lam;
+    s->wpi = c.wpi;
+    s->cs = c.cs;
+    s->ds = c.ds;
+    s->pa = c.pa;
+    s->pu = c.pu;
+    s->fa = c.fa;
 }
 
 hipEvent_t next_event(od_system* s)
@@ -612,3 +632,5 @@ od_status od_get_kernel_times(od_system* s, double* ms, int64_t* launches)
 }
 
 }  // extern "C"
+
+#include "batch_api.inc"
