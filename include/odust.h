@@ -252,6 +252,57 @@ od_status od_batch_get_step_events(od_batch* b, int32_t system, uint8_t* ev_host
 od_status od_batch_set_timing(od_batch* b, int32_t enable);
 od_status od_batch_get_kernel_times(od_batch* b, double* ms_host, int64_t* launches_host);
 
+/* ---- charge warm start --------------------------------------------------- */
+
+/* Floating charge (C) of an isolated grain of the given radius (m) in the
+ * plasma: the root of I_i + I_e = 0 with the OML currents of the "oml"
+ * charging model (Section 2; ion current of the drifting Maxwellian).
+ * Host computation; used to start charges near equilibrium. */
+od_status od_oml_floating_charge(const od_plasma* plasma, double radius, double* q_host);
+
+/* ---- surrogate network --------------------------------------------------- */
+
+/* A fully connected network 5 -> 128 -> 128 -> 128 -> 16 (tanh on hidden
+ * layers, FP32) trained and evaluated by the library's kernels (matrix
+ * products on the matrix cores).  It learns a map from five inputs to
+ * sixteen outputs; the caller chooses their meaning (here: Mach number,
+ * grain radius, grain spacing, collision frequency, T_e/T_i -> charge and
+ * axial force of each grain of an 8-grain chain).  Parameters are one flat
+ * float vector of 35,856 values: for layers l = 1..4, W_l [in][out] then
+ * b_l [out].  Inputs are mapped from the box [in_lo, in_hi] to [-1, 1];
+ * outputs are produced as out_mean + out_std * (network output). */
+typedef struct od_mlp od_mlp;
+typedef struct {
+    int32_t epochs;     /* passes over the training set                     */
+    int32_t batch;      /* rows per step, 1..4096, <= n                      */
+    double lr;          /* Adam learning rate at the first step              */
+    double lr_final;    /* at the last step (exponential decay in between)  */
+    uint64_t seed;      /* shuffling stream                                  */
+} od_train_cfg;
+
+/* Glorot-uniform weights drawn from Philox(seed), zero biases, identity
+ * normalisation. */
+od_status od_mlp_create(uint64_t seed, void* hip_stream, od_mlp** out);
+void od_mlp_destroy(od_mlp* q);
+od_status od_mlp_get_params(od_mlp* q, float* params_host);
+od_status od_mlp_set_params(od_mlp* q, const float* params_host);
+od_status od_mlp_set_normalization(od_mlp* q, const float* in_lo_host, const float* in_hi_host,
+                                   const float* out_mean_host, const float* out_std_host);
+/* Y_host[n][16] for X_host[n][5] (raw units); inside_host[n] (may be NULL) is
+ * 1 where every input lies inside the normalisation box, else 0 (callers fall
+ * back to the full method there). */
+od_status od_mlp_predict(od_mlp* q, const float* X_host, int64_t n, float* Y_host, int32_t* inside_host);
+/* Mean-squared error and its gradient (grad_host[35856]) on n <= 4096 rows of
+ * already normalised inputs Xn_host[n][5] and standardised targets
+ * Tn_host[n][16]. */
+od_status od_mlp_loss_grad(od_mlp* q, const float* Xn_host, const float* Tn_host, int64_t n,
+                           float* grad_host, double* loss);
+/* Adam training on raw X_host[n][5], T_host[n][16] (normalised on the device
+ * with the current normalisation); loss_per_epoch_host[epochs] (may be NULL)
+ * receives the mean standardised squared error of each epoch. */
+od_status od_mlp_train(od_mlp* q, const float* X_host, const float* T_host, int64_t n,
+                       const od_train_cfg* cfg, double* loss_per_epoch_host);
+
 #ifdef __cplusplus
 }
 #endif

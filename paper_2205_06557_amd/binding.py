@@ -65,6 +65,14 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_2205_06557_amd.build` (no CPU fallback exists)")
+        # PyTorch ships its own HIP runtime.  Loading it first makes the
+        # library bind to that same runtime (one HIP/HSA runtime per process),
+        # so PyTorch's streams and memory are valid handles for the library;
+        # loading the library first would bring in a second runtime.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         vp, i64, u64 = C.c_void_p, C.c_int64, C.c_uint64
         L.od_init_system.argtypes = [C.POINTER(Plasma), C.POINTER(Sim), C.POINTER(Dust), C.c_int32,
@@ -442,3 +450,112 @@ class BatchMember:
 
     def charges(self):
         return self.b.charges(self.s)
+
+
+class TrainCfg(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_double),
+                ("lr_final", C.c_double), ("seed", C.c_uint64)]
+
+
+_mlp_sigs = False
+MLP_PARAMS = 35856
+
+
+def _mlp_lib():
+    global _mlp_sigs
+    L = lib()
+    if not _mlp_sigs:
+        vp, i64 = C.c_void_p, C.c_int64
+        fp, dp = C.POINTER(C.c_float), C.POINTER(C.c_double)
+        L.od_mlp_create.argtypes = [C.c_uint64, vp, C.POINTER(vp)]
+        L.od_mlp_destroy.argtypes = [vp]
+        L.od_mlp_destroy.restype = None
+        L.od_mlp_get_params.argtypes = [vp, fp]
+        L.od_mlp_set_params.argtypes = [vp, fp]
+        L.od_mlp_set_normalization.argtypes = [vp, fp, fp, fp, fp]
+        L.od_mlp_predict.argtypes = [vp, fp, i64, fp, C.POINTER(C.c_int32)]
+        L.od_mlp_loss_grad.argtypes = [vp, fp, fp, i64, fp, dp]
+        L.od_mlp_train.argtypes = [vp, fp, fp, i64, C.POINTER(TrainCfg), dp]
+        L.od_oml_floating_charge.argtypes = [C.POINTER(Plasma), C.c_double, dp]
+        for name in ("od_mlp_create", "od_mlp_get_params", "od_mlp_set_params", "od_mlp_set_normalization",
+                     "od_mlp_predict", "od_mlp_loss_grad", "od_mlp_train", "od_oml_floating_charge"):
+            getattr(L, name).restype = C.c_int
+        _mlp_sigs = True
+    return L
+
+
+def oml_floating_charge(w, radius: float) -> float:
+    """Floating charge (C) of an isolated grain of `radius` in workload w's plasma."""
+    pl = Plasma(w.Te, w.Ti, w.n_inf, w.m_i, w.mach, w.nu_in, w.E_ext)
+    q = C.c_double(0)
+    _check(_mlp_lib().od_oml_floating_charge(C.byref(pl), float(radius), C.byref(q)))
+    return q.value
+
+
+def _f32(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+class Mlp:
+    """The 5 -> 128 -> 128 -> 128 -> 16 surrogate network on the GPU."""
+
+    def __init__(self, seed: int = 0, stream=None):
+        h = C.c_void_p()
+        if stream is None:
+            stream = _torch_stream()
+        _check(_mlp_lib().od_mlp_create(int(seed), stream, C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _mlp_lib().od_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def params(self) -> np.ndarray:
+        p = np.zeros(MLP_PARAMS, dtype=np.float32)
+        _check(_mlp_lib().od_mlp_get_params(self._h, _ptr(p, C.c_float)))
+        return p
+
+    def set_params(self, p):
+        p = _f32(p)
+        assert p.size == MLP_PARAMS
+        _check(_mlp_lib().od_mlp_set_params(self._h, _ptr(p, C.c_float)))
+
+    def set_normalization(self, in_lo, in_hi, out_mean, out_std):
+        a, b, c, d = _f32(in_lo), _f32(in_hi), _f32(out_mean), _f32(out_std)
+        _check(_mlp_lib().od_mlp_set_normalization(self._h, _ptr(a, C.c_float), _ptr(b, C.c_float),
+                                                    _ptr(c, C.c_float), _ptr(d, C.c_float)))
+
+    def predict(self, X):
+        X = _f32(X).reshape(-1, 5)
+        n = X.shape[0]
+        Y = np.zeros((n, 16), dtype=np.float32)
+        inside = np.zeros(n, dtype=np.int32)
+        _check(_mlp_lib().od_mlp_predict(self._h, _ptr(X, C.c_float), n, _ptr(Y, C.c_float),
+                                         _ptr(inside, C.c_int32)))
+        return Y, inside.astype(bool)
+
+    def loss_grad(self, Xn, Tn):
+        Xn = _f32(Xn).reshape(-1, 5)
+        Tn = _f32(Tn).reshape(-1, 16)
+        g = np.zeros(MLP_PARAMS, dtype=np.float32)
+        L = C.c_double(0)
+        _check(_mlp_lib().od_mlp_loss_grad(self._h, _ptr(Xn, C.c_float), _ptr(Tn, C.c_float),
+                                           Xn.shape[0], _ptr(g, C.c_float), C.byref(L)))
+        return L.value, g
+
+    def train(self, X, T, epochs: int, batch: int, lr: float = 2e-3, lr_final: float = 5e-5,
+              seed: int = 0):
+        X = _f32(X).reshape(-1, 5)
+        T = _f32(T).reshape(-1, 16)
+        cfg = TrainCfg(int(epochs), int(batch), float(lr), float(lr_final), int(seed))
+        hist = np.zeros(int(epochs))
+        _check(_mlp_lib().od_mlp_train(self._h, _ptr(X, C.c_float), _ptr(T, C.c_float), X.shape[0],
+                                       C.byref(cfg), _ptr(hist)))
+        return hist

@@ -634,3 +634,38 @@ od_status od_get_kernel_times(od_system* s, double* ms, int64_t* launches)
 }  // extern "C"
 
 #include "batch_api.inc"
+#include "mlp_api.inc"
+
+extern "C" od_status od_oml_floating_charge(const od_plasma* P, double a, double* q)
+{
+    if (!P || !q || !(a > 0) || !(P->T_e > 0) || !(P->T_i > 0) || !(P->n_inf > 0) || !(P->m_i > 0))
+        return fail(OD_EINVAL, "bad argument");
+    // currents in A as functions of the grain charge Q (C); OML forms of the
+    // "oml" charging model: electrons Boltzmann-repelled, ions collected with
+    // the OML cross-section from the drifting Maxwellian.
+    const double ve = std::sqrt(8.0 * kKB * P->T_e / (kPI * kME));
+    const double vt = std::sqrt(2.0 * kKB * P->T_i / P->m_i);
+    const double cs = std::sqrt(kKB * P->T_e / P->m_i);
+    const double s = P->mach * cs / vt;
+    auto total = [&](double Q) {
+        const double phi = Q / (4.0 * kPI * kEPS0 * a);
+        const double x = kQE * phi / (kKB * P->T_e);
+        const double Ie = -kPI * a * a * P->n_inf * kQE * ve * (phi < 0 ? std::exp(x) : 1.0 + x);
+        const double chi = phi < 0 ? -kQE * phi / (kKB * P->T_i) : 0.0;
+        const double br = s < 1e-6 ? 2.0 / std::sqrt(kPI) * (1.0 + chi)
+                                   : std::exp(-s * s) / std::sqrt(kPI) + (s * s + 0.5 + chi) * std::erf(s) / s;
+        return kPI * a * a * P->n_inf * kQE * vt * br + Ie;
+    };
+    // bracket: total(0) < 0 (electrons dominate); grow a negative bound
+    double lo = -kQE, hi = 0.0;
+    int guard = 0;
+    while (total(lo) < 0.0 && guard++ < 200) lo *= 2.0;
+    if (total(lo) < 0.0) return fail(OD_ENUMERIC, "no floating charge found");
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (total(mid) > 0.0) lo = mid; else hi = mid;
+        if (hi - lo <= 1e-15 * std::fabs(lo)) break;
+    }
+    *q = 0.5 * (lo + hi);
+    return OD_OK;
+}

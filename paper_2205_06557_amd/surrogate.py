@@ -1,0 +1,291 @@
+"""Learned surrogate of the self-consistent dust-chain result.
+
+A network (trained and evaluated by the library's kernels, ``binding.Mlp``)
+maps five inputs -- Mach number, grain radius (um), spacing of the grains
+(Debye lengths), collision frequency (units of omega_pi), T_e/T_i -- to the
+time-averaged charge and axial force of each grain of a vertical chain of
+eight grains.  Training data come from the batched solver (``binding.Batch``)
+run on inputs drawn uniformly in the input box.  Uses:
+
+* warm start: the predicted charges start a full simulation near its
+  self-consistent state;
+* fast evaluator: charges and forces without simulating, with the full
+  method as the fallback outside the input box and as the judge of error.
+
+Targets are made dimensionless before training: charge by
+4 pi eps0 a k_B T_e / e (grain potential in units of k_B T_e / e) and force
+by a^2 n k_B T_e.
+
+Command line (GPU):
+    python -m paper_2205_06557_amd.surrogate pipeline --out DIR [--runs 1024 --n-ions 16384 --steps 3000]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import workloads as W
+
+FEATURES = ("mach", "radius_um", "spacing_debye", "nu_over_wpi", "te_over_ti")
+BOX_LO = np.array([0.3, 2.0, 0.25, 0.02, 10.0])
+BOX_HI = np.array([2.0, 10.0, 1.0, 0.3, 100.0])
+N_GRAINS = 8
+TE_EV = 1.0
+N_INF = 1e14
+
+
+def sweep_inputs(n: int, seed: int, lo=BOX_LO, hi=BOX_HI) -> np.ndarray:
+    """n input points uniform in the box (seeded Philox stream)."""
+    rng = np.random.Generator(np.random.Philox(key=[seed, 4]))
+    return lo + (hi - lo) * rng.uniform(0.0, 1.0, size=(n, 5))
+
+
+def chain_workload(x5: Sequence[float], n_ions: int, steps: int, seed: int, system_id: int,
+                   q0: Optional[Sequence[float]] = None, n_discard: Optional[int] = None) -> W.Workload:
+    """The 8-grain vertical chain for one input point: grains of radius a on the
+    axis at z_k = (k - 3.5) d, cylinder R = 3 r_De, H = 7 d + 5 r_De, argon at
+    T_e = 1 eV, n = 1e14 m^-3, dt = 0.01/omega_pi, self-consistent charging.
+    q0: initial charges (C), default 0."""
+    mach, a_um, d_l, nu_w, tt = (float(v) for v in x5)
+    te = W.ev_to_kelvin(TE_EV)
+    lam = W.debye_length(te, N_INF)
+    wpi = W.ion_plasma_frequency(N_INF, W.M_ARGON)
+    a = a_um * 1e-6
+    d = d_l * lam
+    q0 = [0.0] * N_GRAINS if q0 is None else list(q0)
+    dust = [(0.0, 0.0, (k - 3.5) * d, a, float(q0[k])) for k in range(N_GRAINS)]
+    return W.Workload(Te=te, Ti=te / tt, n_inf=N_INF, m_i=W.M_ARGON, mach=mach, nu_in=nu_w * wpi,
+                      E_ext=float("nan"), R=3 * lam, H=7 * d + 5 * lam, dt=0.01 / wpi,
+                      n_ions=int(n_ions), n_steps=int(steps),
+                      n_discard=int(steps // 2 if n_discard is None else n_discard), seed=seed,
+                      system_id=system_id, charge_mode=W.CHARGE_CONSISTENT, dust=dust,
+                      name=f"chain8 {x5}")
+
+
+def charge_scale(x5) -> float:
+    """C per unit of normalised charge: 4 pi eps0 a k_B T_e / e."""
+    te = W.ev_to_kelvin(TE_EV)
+    return 4 * math.pi * W.EPS0 * float(x5[1]) * 1e-6 * W.KB * te / W.QE
+
+
+def force_scale(x5) -> float:
+    """N per unit of normalised force: a^2 n k_B T_e."""
+    te = W.ev_to_kelvin(TE_EV)
+    a = float(x5[1]) * 1e-6
+    return a * a * N_INF * W.KB * te
+
+
+def to_targets(x5, q_c, fz_n) -> np.ndarray:
+    return np.concatenate([np.asarray(q_c) / charge_scale(x5), np.asarray(fz_n) / force_scale(x5)])
+
+
+def from_targets(x5, t16):
+    t16 = np.asarray(t16, dtype=np.float64)
+    return t16[:N_GRAINS] * charge_scale(x5), t16[N_GRAINS:] * force_scale(x5)
+
+
+def oml_charge(x5) -> float:
+    from . import binding as B
+    w = chain_workload(x5, 16, 2, 0, 0)
+    return B.oml_floating_charge(w, float(x5[1]) * 1e-6)
+
+
+def run_plain(X: np.ndarray, n_ions: int, steps: int, seed: int, start: str = "oml",
+              q0: Optional[np.ndarray] = None, batch_size: int = 512, graph: int = 10,
+              log=None) -> np.ndarray:
+    """Runs the full method for every input row (batched) and returns the
+    normalised targets [n, 16]: time-averaged charge and total axial force
+    (Eqs. (1)-(4) summed) of each grain over the second half of the run.
+    start: "oml" (isolated-grain floating charge), "zero", or "given" (q0 [n, 8] in C)."""
+    from . import binding as B
+    n = X.shape[0]
+    T = np.zeros((n, 16))
+    for b0 in range(0, n, batch_size):
+        rows = range(b0, min(n, b0 + batch_size))
+        ws = []
+        for r in rows:
+            if start == "oml":
+                q = [oml_charge(X[r])] * N_GRAINS
+            elif start == "given":
+                q = list(q0[r])
+            else:
+                q = None
+            ws.append(chain_workload(X[r], n_ions, steps, seed, r, q))
+        t0 = time.time()
+        b = B.Batch(ws)
+        b.autotune(None)
+        if graph and steps % graph == 0:
+            b.set_graph(graph)
+        done = 0
+        chunk = max(graph, 500 // graph * graph) if graph else 500
+        while done < steps:
+            k = min(chunk, steps - done)
+            b.step(k)
+            b.sync()
+            done += k
+            if log:
+                log(f"  runs {b0}..{rows[-1]}: step {done}/{steps} ({time.time() - t0:.1f} s)")
+        for i, r in enumerate(rows):
+            _, qa = b.charges(i)
+            F = b.forces(i, 1)
+            T[r] = to_targets(X[r], qa, F[:, :, 2].sum(axis=1))
+        b.close()
+    return T
+
+
+class Surrogate:
+    """Trained network plus its normalisation; raw inputs in, physical outputs out."""
+
+    def __init__(self, mlp, t_mean, t_std):
+        self.mlp, self.t_mean, self.t_std = mlp, t_mean, t_std
+
+    @classmethod
+    def train(cls, X: np.ndarray, T: np.ndarray, epochs: int = 400, batch: int = 128,
+              lr: float = 2e-3, lr_final: float = 2e-5, seed: int = 0):
+        from . import binding as B
+        mlp = B.Mlp(seed)
+        mean = T.mean(axis=0)
+        std = T.std(axis=0) + 1e-12
+        mlp.set_normalization(BOX_LO, BOX_HI, mean, std)
+        hist = mlp.train(X, T, epochs=epochs, batch=batch, lr=lr, lr_final=lr_final, seed=seed)
+        s = cls(mlp, mean, std)
+        s.history = hist
+        return s
+
+    def predict_targets(self, X):
+        return self.mlp.predict(X)
+
+    def predict(self, X):
+        """(Q [n, 8] in C, F_z [n, 8] in N, inside [n]); outside the input box
+        the caller must run the full method."""
+        Y, inside = self.mlp.predict(X)
+        Q = np.zeros((len(X), N_GRAINS))
+        F = np.zeros((len(X), N_GRAINS))
+        for r in range(len(X)):
+            Q[r], F[r] = from_targets(X[r], Y[r])
+        return Q, F, inside
+
+
+def steps_to_converge(trace: np.ndarray, q_ref: np.ndarray, block: int, tol: float) -> Optional[int]:
+    """First step count at which the mean charge of a block of `block` steps is
+    within `tol` (relative) of q_ref for every grain; trace [steps, grains]."""
+    nb = trace.shape[0] // block
+    for k in range(nb):
+        m = trace[k * block:(k + 1) * block].mean(axis=0)
+        if np.all(np.abs(m / q_ref - 1.0) <= tol):
+            return (k + 1) * block
+    return None
+
+
+def charge_trace(x5, n_ions: int, steps: int, seed: int, q0, block: int = 200):
+    """Charges of a single chain run, sampled every step (batch of one)."""
+    from . import binding as B
+    w = chain_workload(x5, n_ions, steps, seed, 0, q0)
+    s = B.System(w)
+    tr = np.zeros((steps, N_GRAINS))
+    t0 = time.time()
+    for k in range(steps):
+        s.step(1)
+        if (k + 1) % block == 0 or k + 1 == steps:
+            pass
+        tr[k] = s.charges()[0] if (k % 10 == 0 or k + 1 == steps) else np.nan
+    s.sync()
+    # fill the unsampled steps by holding the last sample (block means only)
+    last = tr[0]
+    for k in range(steps):
+        if np.isnan(tr[k, 0]):
+            tr[k] = last
+        else:
+            last = tr[k]
+    return tr, time.time() - t0
+
+
+def pipeline(out: str, runs: int, n_ions: int, steps: int, test_runs: int, eval_ions: int,
+             eval_steps: int, epochs: int, seed: int = 11):
+    os.makedirs(out, exist_ok=True)
+
+    def log(m):
+        print(m, flush=True)
+
+    res = {"runs": runs, "n_ions": n_ions, "steps": steps, "test_runs": test_runs}
+    t0 = time.time()
+    X = sweep_inputs(runs, seed)
+    log(f"[surrogate] training set: {runs} chain runs, N={n_ions}, {steps} steps")
+    T = run_plain(X, n_ions, steps, seed=seed, log=log)
+    res["gen_s"] = time.time() - t0
+    np.savez(os.path.join(out, "train.npz"), X=X, T=T)
+    Xt = sweep_inputs(test_runs, seed + 1)
+    log(f"[surrogate] held-out set: {test_runs} runs, two seeds each (noise floor of the judge)")
+    Ta = run_plain(Xt, n_ions, steps, seed=seed + 2, log=log)
+    Tb = run_plain(Xt, n_ions, steps, seed=seed + 3, log=log)
+    np.savez(os.path.join(out, "test.npz"), X=Xt, Ta=Ta, Tb=Tb)
+    t1 = time.time()
+    sur = Surrogate.train(X, T, epochs=epochs, seed=seed)
+    res["train_s"] = time.time() - t1
+    res["loss_first_last"] = [float(sur.history[0]), float(sur.history[-1])]
+    np.save(os.path.join(out, "params.npy"), sur.mlp.params())
+    np.savez(os.path.join(out, "norm.npz"), mean=sur.t_mean, std=sur.t_std)
+    t2 = time.time()
+    P, inside = sur.predict_targets(Xt)
+    res["predict_s_per_point"] = (time.time() - t2) / len(Xt)
+    judge = 0.5 * (Ta + Tb)
+    q_err = np.abs(P[:, :8] / judge[:, :8] - 1.0)
+    q_noise = np.abs(Ta[:, :8] / Tb[:, :8] - 1.0) / math.sqrt(2)
+    fscale = np.abs(judge[:, 8:]).mean(axis=1, keepdims=True)
+    f_err = np.abs(P[:, 8:] - judge[:, 8:]) / fscale
+    f_noise = np.abs(Ta[:, 8:] - Tb[:, 8:]) / fscale / math.sqrt(2)
+    res["charge_rel_err"] = {"median": float(np.median(q_err)), "p90": float(np.percentile(q_err, 90)),
+                             "mean": float(q_err.mean())}
+    res["charge_noise_of_judge"] = {"median": float(np.median(q_noise)), "mean": float(q_noise.mean())}
+    res["force_rel_err"] = {"median": float(np.median(f_err)), "p90": float(np.percentile(f_err, 90)),
+                            "mean": float(f_err.mean())}
+    res["force_noise_of_judge"] = {"median": float(np.median(f_noise)), "mean": float(f_noise.mean())}
+    res["inside_box"] = int(inside.sum())
+    # warm start vs cold start on one chain at a larger N
+    x5 = np.array([1.0, 5.0, 0.4, 0.1, 33.3])
+    Qp, Fp, _ = sur.predict(x5[None, :])
+    q_oml = oml_charge(x5)
+    log("[surrogate] warm-start study: reference run")
+    ref_tr, ref_s = charge_trace(x5, eval_ions, eval_steps, seed + 5, Qp[0])
+    q_ref = ref_tr[-2000:].mean(axis=0)
+    out_ws = {"x": x5.tolist(), "n_ions": eval_ions, "q_ref_e": (q_ref / W.QE).tolist(),
+              "surrogate_q_e": (Qp[0] / W.QE).tolist(), "oml_q_e": q_oml / W.QE,
+              "surrogate_q_err_vs_ref": float(np.max(np.abs(Qp[0] / q_ref - 1)))}
+    for name, q0 in (("cold", np.zeros(8)), ("oml", np.full(8, q_oml)), ("surrogate", Qp[0])):
+        log(f"[surrogate] warm-start study: {name}")
+        tr, secs = charge_trace(x5, eval_ions, eval_steps, seed + 6, q0)
+        k = steps_to_converge(tr, q_ref, 200, 0.02)
+        out_ws[name] = {"steps_to_2pct": k, "seconds_per_step": secs / eval_steps}
+    res["warm_start"] = out_ws
+    res["total_s"] = time.time() - t0
+    with open(os.path.join(out, "surrogate_result.json"), "w") as f:
+        json.dump(res, f, indent=1)
+    log(json.dumps(res))
+    return res
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    p = sub.add_parser("pipeline")
+    p.add_argument("--out", required=True)
+    p.add_argument("--runs", type=int, default=1024)
+    p.add_argument("--n-ions", type=int, default=1 << 14)
+    p.add_argument("--steps", type=int, default=3000)
+    p.add_argument("--test-runs", type=int, default=64)
+    p.add_argument("--eval-ions", type=int, default=1 << 16)
+    p.add_argument("--eval-steps", type=int, default=8000)
+    p.add_argument("--epochs", type=int, default=400)
+    a = ap.parse_args(argv)
+    pipeline(a.out, a.runs, a.n_ions, a.steps, a.test_runs, a.eval_ions, a.eval_steps, a.epochs)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,99 @@
+"""GPU tests of the surrogate network kernels (matrix-core products, FP32)
+against the FP64 CPU reference, training behaviour, and a miniature run of
+the surrogate pipeline (solver-generated data -> training -> prediction with
+fallback flags -> warm start)."""
+import numpy as np
+import pytest
+
+from oracle import mlp_oracle as M
+from paper_2205_06557_amd import surrogate as S
+from paper_2205_06557_amd import workloads as W
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2205_06557_amd import binding
+    binding.lib()
+    return binding
+
+
+def _identity_norm(net):
+    net.set_normalization(-np.ones(5), np.ones(5), np.zeros(16), np.ones(16))
+
+
+def test_forward_matches_fp64_reference(B):
+    rng = np.random.default_rng(1)
+    net = B.Mlp(3)
+    _identity_norm(net)
+    p = (rng.normal(size=M.N_PARAMS) * 0.2).astype(np.float32)
+    net.set_params(p)
+    X = rng.uniform(-1, 1, size=(1000, 5)).astype(np.float32)
+    Y, inside = net.predict(X)
+    Yr, _ = M.forward(p.astype(np.float64), X.astype(np.float64))
+    err = np.linalg.norm(Y - Yr) / np.linalg.norm(Yr)
+    say("forward rel err", err)
+    assert err < 2e-6
+    assert inside.all()
+    Y2, inside2 = net.predict(np.array([[1.5, 0, 0, 0, 0]], dtype=np.float32))
+    assert not inside2[0]
+
+
+def test_gradients_match_fp64_reference(B):
+    rng = np.random.default_rng(2)
+    net = B.Mlp(4)
+    p = (rng.normal(size=M.N_PARAMS) * 0.15).astype(np.float32)
+    net.set_params(p)
+    X = rng.uniform(-1, 1, size=(256, 5)).astype(np.float32)
+    T = rng.normal(size=(256, 16)).astype(np.float32)
+    L, g = net.loss_grad(X, T)
+    Lr, gr = M.loss_grad(p.astype(np.float64), X.astype(np.float64), T.astype(np.float64))
+    assert L == pytest.approx(Lr, rel=1e-5)
+    k = 0
+    for (i, o) in M.SIZES:
+        for n in (i * o, o):
+            a, r = g[k:k + n], gr[k:k + n]
+            err = np.linalg.norm(a - r) / np.linalg.norm(r)
+            say("grad tensor", k, n, err)
+            assert err < 1e-4
+            k += n
+
+
+def test_training_fits_smooth_function_and_is_reproducible(B):
+    rng = np.random.default_rng(5)
+    X = rng.uniform(-1, 1, size=(2048, 5))
+    A = rng.normal(size=(5, 16))
+    T = np.sin(X @ A) + 0.3 * X[:, :1] ** 2
+    hist = []
+    params = []
+    for _ in range(2):
+        net = B.Mlp(7)
+        _identity_norm(net)
+        h = net.train(X, T, epochs=60, batch=128, lr=3e-3, lr_final=1e-4, seed=9)
+        hist.append(h)
+        params.append(net.params())
+    say("loss first/last", hist[0][0], hist[0][-1])
+    assert hist[0][-1] < hist[0][0] / 30
+    assert np.array_equal(params[0], params[1])
+    assert np.array_equal(hist[0], hist[1])
+
+
+def test_miniature_surrogate_pipeline(B):
+    X = S.sweep_inputs(12, 5)
+    T = S.run_plain(X, n_ions=512, steps=60, seed=5, batch_size=12, graph=10)
+    assert np.isfinite(T).all()
+    assert (T[:, :8] < 0).all()                       # grains charge negatively
+    sur = S.Surrogate.train(X, T, epochs=40, batch=12, seed=1)
+    Q, F, inside = sur.predict(X)
+    assert inside.all() and np.isfinite(Q).all() and np.isfinite(F).all()
+    _, _, ins = sur.predict(np.array([[2.5, 5.0, 0.5, 0.1, 30.0]]))
+    assert not ins[0]                                 # outside the box: fall back
+    # warm start of a chain from the predicted charges
+    w = S.chain_workload(X[0], 1024, 20, 1, 0, Q[0])
+    with B.System(w) as s:
+        q0, _ = s.charges()
+        assert np.allclose(q0, Q[0])
+        s.step(20)
+        s.sync()
