@@ -29,6 +29,21 @@ PEAK_FP32 = 157.3e12          # MI355X published FP32 vector peak (counts packed
 PEAK_HBM = 8.0e12             # MI355X HBM3E, B/s
 
 
+def measured_traffic(kernel: str, n_ions: int):
+    """HBM bytes per launch of `kernel` from the committed memory-counter
+    summary, or None if it is absent, for another size, or the kernel sources
+    have changed since the counters were taken."""
+    from paper_2205_06557_amd import pmc_summary as P
+    path = os.path.join(ROOT, "profiles", "step_kernels_traffic.json")
+    if not os.path.exists(path):
+        return None
+    s = json.load(open(path))
+    if s.get("source_sha256") != P.kernel_sources_hash() or s.get("n_ions") != n_ions:
+        return None
+    k = s.get("kernels", {}).get(kernel)
+    return None if k is None else k["traffic_bytes"]
+
+
 def push_bytes_per_ion(prec: int) -> int:
     e = 4 if prec == 0 else 8
     return 3 * e * 3 + 2 * 3 * e + 1      # read x, v, a; write x, v; write event byte
@@ -154,8 +169,8 @@ def main():
         batch_bench(args)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the design for sharding the ion set across GPUs is described in DESIGN.md)",
+        print("bench.py measures one GPU only: there is no multi-GPU path here "
+              "(the ion set would be sharded by target ions, see the design notes)",
               file=sys.stderr)
         sys.exit(2)
 
@@ -227,7 +242,7 @@ def main():
             "peak": PEAK_FP32 / 1e12,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32,
-            "traffic": None,
+            "traffic": None if prec else measured_traffic("pair", N),
             "kernel": "pair_forces",
             "flop_per_pair": FLOP_PER_PAIR,
             "launch_ms": pair_ms,
@@ -238,6 +253,7 @@ def main():
             "peak": PEAK_HBM / 1e9,
             "unit": "GB/s",
             "frac": push_gbs / PEAK_HBM,
+            "traffic": None if prec else measured_traffic("push", N),
             "bytes_per_ion": push_bytes_per_ion(prec),
             "launch_ms": push_ms,
         },

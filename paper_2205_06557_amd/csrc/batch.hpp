@@ -29,9 +29,9 @@ struct PairItem {
 };
 
 struct BatchCtl {
-    unsigned int queue;             // next pair work item
+    unsigned int queue;                 // next pair work item
     unsigned int pad_;
-    unsigned long long nlost;       // length of the lost-ion list
+    unsigned long long n_lost[kSlots];  // lost-list segment lengths
     int status;
     int pad2_[11];
 };
@@ -103,19 +103,23 @@ __global__ __launch_bounds__(256) void push_batch_kernel(float* __restrict__ xs,
                         A + 2 * plane, 3 * plane, S.nsplit, i, n, S.pu, S.ds, ctl, code, coll, lost);
         ev[off + i] = code | (coll ? kEvCollBit : 0);
     }
-    const unsigned long long slot = wave_tally(ctl, code, coll, lost, &bc->nlost);
-    if (lost) lost_list[slot] = make_int2(s, i);
+    const long long at = wave_tally(ctl, code, coll, lost, bc->n_lost, seg_cap(gridDim.x));
+    if (lost) lost_list[at] = make_int2(s, i);
 }
 
+// Block b walks segment b mod kSlots of the lost list (grid: a multiple of
+// kSlots); cap: segment capacity of the push grid.
 __global__ __launch_bounds__(64) void reinject_batch_kernel(float* __restrict__ xs,
                                                             float* __restrict__ vs, long long plane,
                                                             const int2* __restrict__ lost_list,
-                                                            const SysDesc* sys,
+                                                            long long cap, const SysDesc* sys,
                                                             Ctl* __restrict__ ctls, BatchCtl* bc)
 {
-    const long long cnt = (long long)bc->nlost;
-    for (long long k = blockIdx.x * 64 + threadIdx.x; k < cnt; k += (long long)gridDim.x * 64) {
-        const int2 e = lost_list[k];
+    const int slot = blockIdx.x % kSlots, part = blockIdx.x / kSlots, parts = gridDim.x / kSlots;
+    const long long cnt = (long long)bc->n_lost[slot];
+    const int2* seg = lost_list + slot * cap;
+    for (long long k = part * 64 + threadIdx.x; k < cnt; k += (long long)parts * 64) {
+        const int2 e = seg[k];
         const SysDesc& S = sys[e.x];
         float* X = xs + S.off;
         float* V = vs + S.off;
@@ -131,9 +135,9 @@ __global__ __launch_bounds__(64) void finalize_batch_kernel(const SysDesc* sys,
     __shared__ double Qs[kMaxDust];
     const SysDesc& S = sys[blockIdx.x];
     finalize_sys(S.fa, S.ds, ctls + blockIdx.x, Qs);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        bc->queue = 0u;
-        bc->nlost = 0ull;
+    if (blockIdx.x == 0) {
+        bc->n_lost[threadIdx.x] = 0ull;     // blockDim.x == kSlots
+        if (threadIdx.x == 0) bc->queue = 0u;
     }
 }
 

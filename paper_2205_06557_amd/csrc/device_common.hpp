@@ -28,10 +28,17 @@ enum : int { kStNaN = 1, kStPlace = 2, kStOverflow = 4 };
 constexpr double kForceScale = 4294967296.0;    // 2^32: Eq. (1) sums, dimensionless
 constexpr double kMomScale = 4294967296.0;      // 2^32: absorbed velocity sums, c_s
 
+// Event counters are spread over kSlots addresses (slot = block index mod
+// kSlots) so that waves of different blocks do not serialise on one atomic;
+// the lost-ion list is cut into kSlots segments the same way.
+constexpr int kSlots = 64;
+
 // Layout of one system's control block (device memory, int64/double words).
 struct Ctl {
     unsigned long long acc[kMaxDust][8];   // [0..2] Eq.(1) sum, [3] absorbed count, [4..6] sum v
-    unsigned long long cnt[4];             // [0] exits, [1] collisions, [2] lost-list length
+    unsigned long long n_exit[kSlots];     // exits, per slot
+    unsigned long long n_coll[kSlots];     // collisions, per slot
+    unsigned long long n_lost[kSlots];     // lost-list segment lengths
     double Q[kMaxDust];                    // charge, e
     double last[kMaxDust][16];             // [0] Q^n, [1..12] F parts (SI), [13] absorbed count
     double sums[kMaxDust][16];             // running sums over recorded steps

@@ -427,25 +427,35 @@ __device__ __forceinline__ void push_ion(T* __restrict__ X, T* __restrict__ Y, T
     VX[i] = v0; VY[i] = v1; VZ[i] = v2;
 }
 
-// Wave totals of exits and collisions into the system's counters, and a slot
-// in a list (of length *list_len) for every lane with `lost` set.  All lanes
-// of the wave must call it.  Returns the lane's slot (valid if `lost`).
-__device__ __forceinline__ unsigned long long wave_tally(Ctl* __restrict__ ctl, uint8_t code,
-                                                         bool coll, bool lost,
-                                                         unsigned long long* list_len)
+// Capacity of one lost-list segment for a push grid of nblk blocks of 256
+// ions: the blocks of a slot hold at most this many ions, so no segment can
+// overflow.
+__host__ __device__ inline long long seg_cap(int nblk)
 {
+    return (long long)((nblk + kSlots - 1) / kSlots) * 256;
+}
+
+// Wave totals of exits and collisions into the system's counters (slot of
+// this block), and a place in the slot's segment of the lost list (segment
+// lengths in seg_len[kSlots], capacity cap) for every lane with `lost` set.
+// All lanes of the wave must call it.  Returns the lane's list index (valid
+// if `lost`).
+__device__ __forceinline__ long long wave_tally(Ctl* __restrict__ ctl, uint8_t code, bool coll,
+                                                bool lost, unsigned long long* seg_len, long long cap)
+{
+    const int slot = blockIdx.x % kSlots;
     const unsigned long long ex = __ballot(code == kEvExit);
     const unsigned long long cl = __ballot(coll);
     const unsigned long long ls = __ballot(lost);
     const int lane = threadIdx.x & 63;
     unsigned long long base = 0;
     if (lane == 0) {
-        if (ex) atomicAdd(&ctl->cnt[0], (unsigned long long)__popcll(ex));
-        if (cl) atomicAdd(&ctl->cnt[1], (unsigned long long)__popcll(cl));
-        if (ls) base = atomicAdd(list_len, (unsigned long long)__popcll(ls));
+        if (ex) atomicAdd(&ctl->n_exit[slot], (unsigned long long)__popcll(ex));
+        if (cl) atomicAdd(&ctl->n_coll[slot], (unsigned long long)__popcll(cl));
+        if (ls) base = atomicAdd(&seg_len[slot], (unsigned long long)__popcll(ls));
     }
     base = __shfl(base, 0, 64);
-    return base + __popcll(ls & ((1ull << lane) - 1ull));
+    return slot * cap + (long long)base + __popcll(ls & ((1ull << lane) - 1ull));
 }
 
 // Push of one system: one ion per thread.
@@ -466,8 +476,8 @@ __global__ __launch_bounds__(256) void push_kernel(T* __restrict__ xs, T* __rest
                     as + 2 * Npad, 0, 1, i, n, p, ds, ctl, code, coll, lost);
         ev[i] = code | (coll ? kEvCollBit : 0);
     }
-    const unsigned long long slot = wave_tally(ctl, code, coll, lost, &ctl->cnt[2]);
-    if (lost) lost_list[slot] = i;
+    const long long at = wave_tally(ctl, code, coll, lost, ctl->n_lost, seg_cap(gridDim.x));
+    if (lost) lost_list[at] = i;
 }
 
 // New boundary position and velocity of listed ion i (Appendix B).
@@ -483,19 +493,21 @@ __device__ __forceinline__ void reinject_ion(T* __restrict__ X, T* __restrict__ 
     VX[i] = (T)o[3]; VY[i] = (T)o[4]; VZ[i] = (T)o[5];
 }
 
-// Reinjection of the ions the push listed.  A fixed grid walks the list,
-// whose length the push left in the control block.
+// Reinjection of the ions the push listed.  Block b walks segment
+// b mod kSlots of the list (length left by the push in n_lost); the grid is
+// a multiple of kSlots.  cap: segment capacity of the push grid.
 template <typename T>
 __global__ __launch_bounds__(64) void reinject_kernel(T* __restrict__ xs, T* __restrict__ vs,
                                                      const int* __restrict__ lost_list, PushArgs p,
-                                                     Ctl* __restrict__ ctl)
+                                                     long long cap, Ctl* __restrict__ ctl)
 {
-    const long long cnt = (long long)ctl->cnt[2];
+    const int slot = blockIdx.x % kSlots, part = blockIdx.x / kSlots, parts = gridDim.x / kSlots;
+    const long long cnt = (long long)ctl->n_lost[slot];
     const uint64_t n = (uint64_t)ctl->step;
     const int Npad = p.Npad;
-    for (long long k = blockIdx.x * 64 + threadIdx.x; k < cnt; k += (long long)gridDim.x * 64)
-        reinject_ion<T>(xs, xs + Npad, xs + 2 * Npad, vs, vs + Npad, vs + 2 * Npad, lost_list[k],
-                        n, p);
+    const int* seg = lost_list + slot * cap;
+    for (long long k = part * 64 + threadIdx.x; k < cnt; k += (long long)parts * 64)
+        reinject_ion<T>(xs, xs + Npad, xs + 2 * Npad, vs, vs + Npad, vs + 2 * Npad, seg[k], n, p);
 }
 
 // ---------------------------------------------------------------------------
@@ -568,12 +580,15 @@ __device__ __forceinline__ void finalize_sys(const FinalArgs& f, const DustSet& 
         if (bad) atomicOr(&ctl->status, kStNaN);
     }
     __syncthreads();
+    // event counters: one slot per lane (blockDim.x == kSlots == 64)
+    const double ne = wave_sum((double)ctl->n_exit[d]);
+    const double nc = wave_sum((double)ctl->n_coll[d]);
+    ctl->n_exit[d] = 0ull;
+    ctl->n_coll[d] = 0ull;
+    ctl->n_lost[d] = 0ull;
     if (d == 0) {
-        ctl->last_exit = (long long)ctl->cnt[0];
-        ctl->last_coll = (long long)ctl->cnt[1];
-        ctl->cnt[0] = 0ull;
-        ctl->cnt[1] = 0ull;
-        ctl->cnt[2] = 0ull;
+        ctl->last_exit = (long long)ne;
+        ctl->last_coll = (long long)nc;
         if (n >= f.n_discard) ctl->nrec += 1;
         ctl->step = n + 1;
     }

@@ -34,7 +34,7 @@ constexpr double kPI = 3.14159265358979323846;
 constexpr int kPairBlock = 256;
 constexpr int kPairTile = 256;
 constexpr int kPad = 256;
-constexpr int kReinjGrid = 128;
+constexpr int kReinjGrid = 2 * odk::kSlots;   // a multiple of the lost-list segments
 
 thread_local std::string g_err;
 
@@ -309,10 +309,10 @@ od_status launch_step(od_system* s)
         } else if (k == 2) {
             if (s->prec == OD_PREC_FP32)
                 odk::reinject_kernel<float><<<kReinjGrid, 64, 0, s->stream>>>(
-                    (float*)s->x, (float*)s->v, s->lost, s->pu, s->ctl);
+                    (float*)s->x, (float*)s->v, s->lost, s->pu, odk::seg_cap(gq), s->ctl);
             else
                 odk::reinject_kernel<double><<<kReinjGrid, 64, 0, s->stream>>>(
-                    (double*)s->x, (double*)s->v, s->lost, s->pu, s->ctl);
+                    (double*)s->x, (double*)s->v, s->lost, s->pu, odk::seg_cap(gq), s->ctl);
         } else {
             odk::finalize_kernel<<<1, 64, 0, s->stream>>>(s->fa, s->ds, s->ctl);
         }
@@ -377,7 +377,7 @@ od_status od_init_system(const od_plasma* plasma, const od_sim* sim, const od_du
     s->v = dev_alloc(s, vec);
     s->a = dev_alloc(s, vec);
     s->ev = (uint8_t*)dev_alloc(s, (size_t)s->Npad);
-    s->lost = (int*)dev_alloc(s, (size_t)s->Npad * sizeof(int));
+    s->lost = (int*)dev_alloc(s, (size_t)odk::kSlots * odk::seg_cap((int)((s->N + 255) / 256)) * sizeof(int));
     s->ctl = (odk::Ctl*)dev_alloc(s, sizeof(odk::Ctl));
     if (!s->x || !s->v || !s->a || !s->ev || !s->lost || !s->ctl) {
         od_destroy(s);

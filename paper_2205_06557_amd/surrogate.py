@@ -17,7 +17,8 @@ Targets are made dimensionless before training: charge by
 by a^2 n k_B T_e.
 
 Command line (GPU):
-    python -m paper_2205_06557_amd.surrogate pipeline --out DIR [--runs 1024 --n-ions 16384 --steps 3000]
+    python -m paper_2205_06557_amd.surrogate generate --out DIR --tag train --start 0 --count 512
+    python -m paper_2205_06557_amd.surrogate evaluate --data DIR --out DIR
 """
 from __future__ import annotations
 
@@ -47,12 +48,19 @@ def sweep_inputs(n: int, seed: int, lo=BOX_LO, hi=BOX_HI) -> np.ndarray:
     return lo + (hi - lo) * rng.uniform(0.0, 1.0, size=(n, 5))
 
 
+DT_WPI = 0.04      # time step of the surrogate protocol, units of 1/omega_pi
+AVG_STEPS = 2000   # trailing steps averaged for the targets
+
+
 def chain_workload(x5: Sequence[float], n_ions: int, steps: int, seed: int, system_id: int,
-                   q0: Optional[Sequence[float]] = None, n_discard: Optional[int] = None) -> W.Workload:
+                   q0: Optional[Sequence[float]] = None, n_discard: Optional[int] = None,
+                   dt_wpi: float = DT_WPI) -> W.Workload:
     """The 8-grain vertical chain for one input point: grains of radius a on the
     axis at z_k = (k - 3.5) d, cylinder R = 3 r_De, H = 7 d + 5 r_De, argon at
-    T_e = 1 eV, n = 1e14 m^-3, dt = 0.01/omega_pi, self-consistent charging.
-    q0: initial charges (C), default 0."""
+    T_e = 1 eV, n = 1e14 m^-3, self-consistent charging, dt = dt_wpi/omega_pi
+    (0.04 by default: the grain charging time is ~70/omega_pi, so a 6,000-step
+    run spans ~3.4 charging times).  q0: initial charges (C), default 0;
+    n_discard: default steps - AVG_STEPS."""
     mach, a_um, d_l, nu_w, tt = (float(v) for v in x5)
     te = W.ev_to_kelvin(TE_EV)
     lam = W.debye_length(te, N_INF)
@@ -62,9 +70,10 @@ def chain_workload(x5: Sequence[float], n_ions: int, steps: int, seed: int, syst
     q0 = [0.0] * N_GRAINS if q0 is None else list(q0)
     dust = [(0.0, 0.0, (k - 3.5) * d, a, float(q0[k])) for k in range(N_GRAINS)]
     return W.Workload(Te=te, Ti=te / tt, n_inf=N_INF, m_i=W.M_ARGON, mach=mach, nu_in=nu_w * wpi,
-                      E_ext=float("nan"), R=3 * lam, H=7 * d + 5 * lam, dt=0.01 / wpi,
+                      E_ext=float("nan"), R=3 * lam, H=7 * d + 5 * lam, dt=dt_wpi / wpi,
                       n_ions=int(n_ions), n_steps=int(steps),
-                      n_discard=int(steps // 2 if n_discard is None else n_discard), seed=seed,
+                      n_discard=int(max(steps - AVG_STEPS, 0) if n_discard is None else n_discard),
+                      seed=seed,
                       system_id=system_id, charge_mode=W.CHARGE_CONSISTENT, dust=dust,
                       name=f"chain8 {x5}")
 
@@ -102,7 +111,7 @@ def run_plain(X: np.ndarray, n_ions: int, steps: int, seed: int, start: str = "o
               log=None) -> np.ndarray:
     """Runs the full method for every input row (batched) and returns the
     normalised targets [n, 16]: time-averaged charge and total axial force
-    (Eqs. (1)-(4) summed) of each grain over the second half of the run.
+    (Eqs. (1)-(4) summed) of each grain over the last AVG_STEPS steps.
     start: "oml" (isolated-grain floating charge), "zero", or "given" (q0 [n, 8] in C)."""
     from . import binding as B
     n = X.shape[0]
@@ -207,25 +216,45 @@ def charge_trace(x5, n_ions: int, steps: int, seed: int, q0, block: int = 200):
     return tr, time.time() - t0
 
 
-def pipeline(out: str, runs: int, n_ions: int, steps: int, test_runs: int, eval_ions: int,
-             eval_steps: int, epochs: int, seed: int = 11):
+def generate(out: str, tag: str, total: int, start: int, count: int, n_ions: int, steps: int,
+             seed: int, run_seed: int):
+    """Rows [start, start + count) of the sweep of `total` inputs (stream `seed`),
+    run with the full method (random stream `run_seed`); saved as DIR/TAG_START.npz."""
+    os.makedirs(out, exist_ok=True)
+    X = sweep_inputs(total, seed)[start:start + count]
+    t0 = time.time()
+    print(f"[surrogate] {tag}: rows {start}..{start + count - 1}, N={n_ions}, {steps} steps", flush=True)
+    T = run_plain(X, n_ions, steps, seed=run_seed, log=lambda m: print(m, flush=True))
+    np.savez(os.path.join(out, f"{tag}_{start:05d}.npz"), X=X, T=T, n_ions=n_ions, steps=steps,
+             seconds=time.time() - t0)
+    print(f"[surrogate] {tag}: done in {time.time() - t0:.1f} s", flush=True)
+
+
+def _load(data: str, tag: str):
+    fs = sorted(f for f in os.listdir(data) if f.startswith(tag + "_") and f.endswith(".npz"))
+    Xs, Ts = [], []
+    for f in fs:
+        z = np.load(os.path.join(data, f))
+        Xs.append(z["X"])
+        Ts.append(z["T"])
+    return np.concatenate(Xs), np.concatenate(Ts)
+
+
+def evaluate(data: str, out: str, epochs: int, eval_ions: int, eval_steps: int, seed: int = 11):
+    """Trains on DATA/train_*.npz, judges against DATA/testa_*.npz and
+    DATA/testb_*.npz (the same held-out inputs, two random streams), and runs
+    the warm-start study; writes OUT/surrogate_result.json."""
     os.makedirs(out, exist_ok=True)
 
     def log(m):
         print(m, flush=True)
 
-    res = {"runs": runs, "n_ions": n_ions, "steps": steps, "test_runs": test_runs}
-    t0 = time.time()
-    X = sweep_inputs(runs, seed)
-    log(f"[surrogate] training set: {runs} chain runs, N={n_ions}, {steps} steps")
-    T = run_plain(X, n_ions, steps, seed=seed, log=log)
-    res["gen_s"] = time.time() - t0
-    np.savez(os.path.join(out, "train.npz"), X=X, T=T)
-    Xt = sweep_inputs(test_runs, seed + 1)
-    log(f"[surrogate] held-out set: {test_runs} runs, two seeds each (noise floor of the judge)")
-    Ta = run_plain(Xt, n_ions, steps, seed=seed + 2, log=log)
-    Tb = run_plain(Xt, n_ions, steps, seed=seed + 3, log=log)
-    np.savez(os.path.join(out, "test.npz"), X=Xt, Ta=Ta, Tb=Tb)
+    X, T = _load(data, "train")
+    Xt, Ta = _load(data, "testa")
+    Xt2, Tb = _load(data, "testb")
+    assert np.array_equal(Xt, Xt2)
+    res = {"train_rows": int(len(X)), "test_rows": int(len(Xt)), "dt_wpi": DT_WPI,
+           "avg_steps": AVG_STEPS}
     t1 = time.time()
     sur = Surrogate.train(X, T, epochs=epochs, seed=seed)
     res["train_s"] = time.time() - t1
@@ -241,12 +270,13 @@ def pipeline(out: str, runs: int, n_ions: int, steps: int, test_runs: int, eval_
     fscale = np.abs(judge[:, 8:]).mean(axis=1, keepdims=True)
     f_err = np.abs(P[:, 8:] - judge[:, 8:]) / fscale
     f_noise = np.abs(Ta[:, 8:] - Tb[:, 8:]) / fscale / math.sqrt(2)
-    res["charge_rel_err"] = {"median": float(np.median(q_err)), "p90": float(np.percentile(q_err, 90)),
-                             "mean": float(q_err.mean())}
-    res["charge_noise_of_judge"] = {"median": float(np.median(q_noise)), "mean": float(q_noise.mean())}
-    res["force_rel_err"] = {"median": float(np.median(f_err)), "p90": float(np.percentile(f_err, 90)),
-                            "mean": float(f_err.mean())}
-    res["force_noise_of_judge"] = {"median": float(np.median(f_noise)), "mean": float(f_noise.mean())}
+
+    def st(a):
+        return {"median": float(np.median(a)), "p90": float(np.percentile(a, 90)), "mean": float(a.mean())}
+    res["charge_rel_err"] = st(q_err)
+    res["charge_noise_of_judge"] = st(q_noise)
+    res["force_rel_err_vs_mean_abs"] = st(f_err)
+    res["force_noise_of_judge"] = st(f_noise)
     res["inside_box"] = int(inside.sum())
     # warm start vs cold start on one chain at a larger N
     x5 = np.array([1.0, 5.0, 0.4, 0.1, 33.3])
@@ -254,17 +284,21 @@ def pipeline(out: str, runs: int, n_ions: int, steps: int, test_runs: int, eval_
     q_oml = oml_charge(x5)
     log("[surrogate] warm-start study: reference run")
     ref_tr, ref_s = charge_trace(x5, eval_ions, eval_steps, seed + 5, Qp[0])
-    q_ref = ref_tr[-2000:].mean(axis=0)
-    out_ws = {"x": x5.tolist(), "n_ions": eval_ions, "q_ref_e": (q_ref / W.QE).tolist(),
-              "surrogate_q_e": (Qp[0] / W.QE).tolist(), "oml_q_e": q_oml / W.QE,
-              "surrogate_q_err_vs_ref": float(np.max(np.abs(Qp[0] / q_ref - 1)))}
+    q_ref = ref_tr[-AVG_STEPS:].mean(axis=0)
+    ws = {"x": x5.tolist(), "n_ions": eval_ions, "steps": eval_steps, "q_ref_e": (q_ref / W.QE).tolist(),
+          "surrogate_q_e": (Qp[0] / W.QE).tolist(), "oml_q_e": q_oml / W.QE,
+          "surrogate_q_err_vs_ref": float(np.max(np.abs(Qp[0] / q_ref - 1))),
+          "reference_seconds": ref_s}
     for name, q0 in (("cold", np.zeros(8)), ("oml", np.full(8, q_oml)), ("surrogate", Qp[0])):
         log(f"[surrogate] warm-start study: {name}")
         tr, secs = charge_trace(x5, eval_ions, eval_steps, seed + 6, q0)
         k = steps_to_converge(tr, q_ref, 200, 0.02)
-        out_ws[name] = {"steps_to_2pct": k, "seconds_per_step": secs / eval_steps}
-    res["warm_start"] = out_ws
-    res["total_s"] = time.time() - t0
+        ws[name] = {"steps_to_2pct": k, "seconds_per_step": secs / eval_steps}
+    t3 = time.time()
+    for _ in range(100):
+        sur.predict(x5[None, :])
+    ws["surrogate_seconds_per_eval"] = (time.time() - t3) / 100
+    res["warm_start"] = ws
     with open(os.path.join(out, "surrogate_result.json"), "w") as f:
         json.dump(res, f, indent=1)
     log(json.dumps(res))
@@ -274,17 +308,27 @@ def pipeline(out: str, runs: int, n_ions: int, steps: int, test_runs: int, eval_
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
-    p = sub.add_parser("pipeline")
-    p.add_argument("--out", required=True)
-    p.add_argument("--runs", type=int, default=1024)
-    p.add_argument("--n-ions", type=int, default=1 << 14)
-    p.add_argument("--steps", type=int, default=3000)
-    p.add_argument("--test-runs", type=int, default=64)
-    p.add_argument("--eval-ions", type=int, default=1 << 16)
-    p.add_argument("--eval-steps", type=int, default=8000)
-    p.add_argument("--epochs", type=int, default=400)
+    g = sub.add_parser("generate")
+    g.add_argument("--out", required=True)
+    g.add_argument("--tag", default="train")
+    g.add_argument("--total", type=int, default=1024)
+    g.add_argument("--start", type=int, default=0)
+    g.add_argument("--count", type=int, default=512)
+    g.add_argument("--n-ions", type=int, default=1 << 14)
+    g.add_argument("--steps", type=int, default=6000)
+    g.add_argument("--seed", type=int, default=11)
+    g.add_argument("--run-seed", type=int, default=11)
+    e = sub.add_parser("evaluate")
+    e.add_argument("--data", required=True)
+    e.add_argument("--out", required=True)
+    e.add_argument("--epochs", type=int, default=600)
+    e.add_argument("--eval-ions", type=int, default=1 << 16)
+    e.add_argument("--eval-steps", type=int, default=10000)
     a = ap.parse_args(argv)
-    pipeline(a.out, a.runs, a.n_ions, a.steps, a.test_runs, a.eval_ions, a.eval_steps, a.epochs)
+    if a.cmd == "generate":
+        generate(a.out, a.tag, a.total, a.start, a.count, a.n_ions, a.steps, a.seed, a.run_seed)
+    else:
+        evaluate(a.data, a.out, a.epochs, a.eval_ions, a.eval_steps)
 
 
 if __name__ == "__main__":
