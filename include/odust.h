@@ -173,6 +173,14 @@ od_status od_set_state(od_system* sys, const void* x_host, const void* v_host, c
  * (float or double as the state). */
 od_status od_get_accelerations(od_system* sys, void* a_host);
 
+/* Source splits of the pair sum (FP32 mode): the sources are cut into nsplit
+ * (1..4) ranges evaluated by separate blocks whose partial accelerations the
+ * push adds in order, so that small systems fill the GPU.  Chosen at
+ * creation for about four blocks per compute unit; changing it changes
+ * rounding only. */
+od_status od_set_pair_split(od_system* sys, int32_t nsplit);
+od_status od_get_pair_split(od_system* sys, int32_t* nsplit);
+
 /* Events of the last step: ev_host[N] bytes (0 none, 1 exited, 2 + d
  * absorbed by grain d; bit 7 set if a charge-exchange collision happened),
  * n_abs_host[n_dust] absorbed counts, *n_exit, *n_coll.  Any may be NULL. */

@@ -559,3 +559,28 @@ class Mlp:
         _check(_mlp_lib().od_mlp_train(self._h, _ptr(X, C.c_float), _ptr(T, C.c_float), X.shape[0],
                                        C.byref(cfg), _ptr(hist)))
         return hist
+
+
+def _split_sigs():
+    L = lib()
+    if not getattr(L, "_split_ok", False):
+        L.od_set_pair_split.argtypes = [C.c_void_p, C.c_int32]
+        L.od_get_pair_split.argtypes = [C.c_void_p, C.POINTER(C.c_int32)]
+        L.od_set_pair_split.restype = C.c_int
+        L.od_get_pair_split.restype = C.c_int
+        L._split_ok = True
+    return L
+
+
+def _system_set_pair_split(self, nsplit: int):
+    _check(_split_sigs().od_set_pair_split(self._h, int(nsplit)))
+
+
+def _system_pair_split(self) -> int:
+    n = C.c_int32(0)
+    _check(_split_sigs().od_get_pair_split(self._h, C.byref(n)))
+    return n.value
+
+
+System.set_pair_split = _system_set_pair_split
+System.pair_split = _system_pair_split

@@ -42,7 +42,8 @@ __device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_read
 // from bc->queue until the list is exhausted (every block leaves when the
 // counter passes n_items); else block b does item b.
 template <int BLOCK, int TJ>
-__global__ __launch_bounds__(BLOCK) void pair_batch_kernel(const float* __restrict__ xs,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8, 8)))
+void pair_batch_kernel(const float* __restrict__ xs,
                                                            float* __restrict__ acc,
                                                            long long plane, const SysDesc* sys,
                                                            Ctl* __restrict__ ctls,

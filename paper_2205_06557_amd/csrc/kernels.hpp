@@ -172,17 +172,28 @@ __device__ __forceinline__ void pair_block_f32(const float* __restrict__ X,
     __syncthreads();
 }
 
+// Pair forces of one system.  The source range is cut into `nsplit` parts
+// (blocks [k * Npad/BLOCK, (k + 1) * Npad/BLOCK) take part k) so that small
+// systems still fill the chip; part k writes its partial acceleration to
+// planes k of `acc` (3 Npad apart), which the push adds in order.
+// Eight waves per SIMD (at most 64 VGPRs) keep the transcendental and LDS
+// latencies of the inner loop hidden.
 template <int BLOCK, int TJ>
-__global__ __launch_bounds__(BLOCK) void pair_forces_f32(const float* __restrict__ xs,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8, 8)))
+void pair_forces_f32(const float* __restrict__ xs,
                                                          float* __restrict__ acc,
                                                          PairArgs p, DustSet ds,
-                                                         Ctl* __restrict__ ctl)
+                                                         Ctl* __restrict__ ctl, int nsplit)
 {
     __shared__ float4 tile[TJ];
     __shared__ double red[BLOCK / 64][kMaxDust][3];
     const int Npad = p.Npad;
-    pair_block_f32<BLOCK, TJ>(xs, xs + Npad, xs + 2 * Npad, blockIdx.x * BLOCK, 0, Npad, p, ds, ctl,
-                              acc, acc + Npad, acc + 2 * Npad, true, tile, red);
+    const int nib = Npad / BLOCK, tiles = Npad / TJ;
+    const int ib = blockIdx.x % nib, k = blockIdx.x / nib;
+    const int jb = (tiles * k / nsplit) * TJ, je = (tiles * (k + 1) / nsplit) * TJ;
+    float* o = acc + (long long)k * 3 * Npad;
+    pair_block_f32<BLOCK, TJ>(xs, xs + Npad, xs + 2 * Npad, ib * BLOCK, jb, je, p, ds, ctl, o,
+                              o + Npad, o + 2 * Npad, k == 0, tile, red);
 }
 
 // Forces, FP64 throughout (precision mode OD_PREC_FP64).
@@ -464,7 +475,7 @@ __global__ __launch_bounds__(256) void push_kernel(T* __restrict__ xs, T* __rest
                                                    const T* __restrict__ as,
                                                    uint8_t* __restrict__ ev,
                                                    int* __restrict__ lost_list, PushArgs p,
-                                                   DustSet ds, Ctl* __restrict__ ctl)
+                                                   DustSet ds, Ctl* __restrict__ ctl, int nsplit)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
     const int Npad = p.Npad;
@@ -473,7 +484,7 @@ __global__ __launch_bounds__(256) void push_kernel(T* __restrict__ xs, T* __rest
     uint8_t code = kEvNone;
     if (i < p.N) {
         push_ion<T>(xs, xs + Npad, xs + 2 * Npad, vs, vs + Npad, vs + 2 * Npad, as, as + Npad,
-                    as + 2 * Npad, 0, 1, i, n, p, ds, ctl, code, coll, lost);
+                    as + 2 * Npad, 3LL * Npad, nsplit, i, n, p, ds, ctl, code, coll, lost);
         ev[i] = code | (coll ? kEvCollBit : 0);
     }
     const long long at = wave_tally(ctl, code, coll, lost, ctl->n_lost, seg_cap(gridDim.x));

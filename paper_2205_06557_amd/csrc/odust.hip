@@ -2,9 +2,10 @@
 // meaning of every argument: include/odust.h).
 //
 // One od_system owns, on one HIP stream:
-//   x, v, a   [3][Npad] structure-of-arrays state, float (FP32 mode) or double
+//   x, v      [3][Npad] structure-of-arrays state, float (FP32 mode) or double
 //             (FP64 mode); Npad = N rounded up to the pair tile, padding slots
 //             parked at a far-away sentinel;
+//   a         [nsplit][3][Npad] partial accelerations of the source splits;
 //   ev        [Npad] per-ion event byte of the last step;
 //   lost      [Npad] indices of the ions the last push removed;
 //   ctl       small control block (charges, int64 fixed-point accumulators,
@@ -13,6 +14,7 @@
 // forces, push, reinjection, finalize) and needs no host synchronisation.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -35,6 +37,7 @@ constexpr int kPairBlock = 256;
 constexpr int kPairTile = 256;
 constexpr int kPad = 256;
 constexpr int kReinjGrid = 2 * odk::kSlots;   // a multiple of the lost-list segments
+constexpr int kMaxSplitSingle = 4;             // source splits of one system's pair sum
 
 thread_local std::string g_err;
 
@@ -88,6 +91,7 @@ struct od_system {
     int prec = 0;
     int64_t N = 0, Npad = 0;
     size_t esz = 4;
+    int nsplit = 1;
     // units
     double lam = 0, wpi = 0, cs = 0;
     odk::DustSet ds{};
@@ -292,8 +296,8 @@ od_status launch_step(od_system* s)
         }
         if (k == 0) {
             if (s->prec == OD_PREC_FP32)
-                odk::pair_forces_f32<kPairBlock, kPairTile><<<gp, kPairBlock, 0, s->stream>>>(
-                    (const float*)s->x, (float*)s->a, s->pa, s->ds, s->ctl);
+                odk::pair_forces_f32<kPairBlock, kPairTile><<<gp * s->nsplit, kPairBlock, 0, s->stream>>>(
+                    (const float*)s->x, (float*)s->a, s->pa, s->ds, s->ctl, s->nsplit);
             else
                 odk::pair_forces_f64<kPairBlock, kPairTile><<<gp, kPairBlock, 0, s->stream>>>(
                     (const double*)s->x, (double*)s->a, s->pa, s->ds, s->ctl);
@@ -301,11 +305,11 @@ od_status launch_step(od_system* s)
             if (s->prec == OD_PREC_FP32)
                 odk::push_kernel<float><<<gq, 256, 0, s->stream>>>(
                     (float*)s->x, (float*)s->v, (const float*)s->a, s->ev, s->lost, s->pu, s->ds,
-                    s->ctl);
+                    s->ctl, s->nsplit);
             else
                 odk::push_kernel<double><<<gq, 256, 0, s->stream>>>(
                     (double*)s->x, (double*)s->v, (const double*)s->a, s->ev, s->lost, s->pu, s->ds,
-                    s->ctl);
+                    s->ctl, 1);
         } else if (k == 2) {
             if (s->prec == OD_PREC_FP32)
                 odk::reinject_kernel<float><<<kReinjGrid, 64, 0, s->stream>>>(
@@ -371,11 +375,24 @@ od_status od_init_system(const od_plasma* plasma, const od_sim* sim, const od_du
     s->N = sim->n_ions;
     s->Npad = (s->N + kPad - 1) / kPad * kPad;
     derive(s);
+    // Source splits of the pair sum: enough blocks for about four per CU.
+    {
+        int dev = 0;
+        hipDeviceProp_t prop{};
+        (void)hipGetDevice(&dev);
+        (void)hipGetDeviceProperties(&prop, dev);
+        const int64_t nib = s->Npad / kPairBlock;
+        const int64_t want = 4 * (int64_t)std::max(prop.multiProcessorCount, 1);
+        s->nsplit = s->prec == OD_PREC_FP32
+                        ? (int)std::min<int64_t>(kMaxSplitSingle, std::max<int64_t>(1, (want + nib - 1) / nib))
+                        : 1;
+        s->nsplit = (int)std::min<int64_t>(s->nsplit, nib);
+    }
 
     const size_t vec = 3 * (size_t)s->Npad * s->esz;
     s->x = dev_alloc(s, vec);
     s->v = dev_alloc(s, vec);
-    s->a = dev_alloc(s, vec);
+    s->a = dev_alloc(s, vec * (s->prec == OD_PREC_FP32 ? kMaxSplitSingle : 1));
     s->ev = (uint8_t*)dev_alloc(s, (size_t)s->Npad);
     s->lost = (int*)dev_alloc(s, (size_t)odk::kSlots * odk::seg_cap((int)((s->N + 255) / 256)) * sizeof(int));
     s->ctl = (odk::Ctl*)dev_alloc(s, sizeof(odk::Ctl));
@@ -572,6 +589,34 @@ od_status od_get_accelerations(od_system* s, void* a)
     od_status st = copy_soa_out(s, s->a, a);
     if (st != OD_OK) return st;
     HIPCHK(hipStreamSynchronize(s->stream));
+    if (s->nsplit > 1) {   // add the partial planes in the push's order
+        std::vector<float> part(3 * (size_t)s->N);
+        float* out = (float*)a;
+        for (int k = 1; k < s->nsplit; ++k) {
+            st = copy_soa_out(s, (const char*)s->a + (size_t)k * 3 * s->Npad * s->esz, part.data());
+            if (st != OD_OK) return st;
+            HIPCHK(hipStreamSynchronize(s->stream));
+            for (size_t i = 0; i < part.size(); ++i) out[i] += part[i];
+        }
+    }
+    return OD_OK;
+}
+
+od_status od_set_pair_split(od_system* s, int32_t nsplit)
+{
+    if (!s) return fail(OD_EINVAL, "null system");
+    if (nsplit < 1 || nsplit > kMaxSplitSingle) return fail(OD_EINVAL, "nsplit must be in [1,%d]", kMaxSplitSingle);
+    if (s->prec != OD_PREC_FP32 && nsplit != 1) return fail(OD_EINVAL, "the FP64 mode does not split");
+    if (nsplit > s->Npad / kPairBlock) return fail(OD_EINVAL, "more splits than source tiles");
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->nsplit = nsplit;
+    return OD_OK;
+}
+
+od_status od_get_pair_split(od_system* s, int32_t* nsplit)
+{
+    if (!s || !nsplit) return fail(OD_EINVAL, "null argument");
+    *nsplit = s->nsplit;
     return OD_OK;
 }
 

@@ -292,8 +292,14 @@ def evaluate(data: str, out: str, epochs: int, eval_ions: int, eval_steps: int, 
     for name, q0 in (("cold", np.zeros(8)), ("oml", np.full(8, q_oml)), ("surrogate", Qp[0])):
         log(f"[surrogate] warm-start study: {name}")
         tr, secs = charge_trace(x5, eval_ions, eval_steps, seed + 6, q0)
-        k = steps_to_converge(tr, q_ref, 200, 0.02)
-        ws[name] = {"steps_to_2pct": k, "seconds_per_step": secs / eval_steps}
+        win = 500
+        errs = [float(np.max(np.abs(tr[k:k + win].mean(axis=0) / q_ref - 1.0)))
+                for k in range(0, eval_steps - win + 1, win)]
+        ws[name] = {"initial_max_rel_err": float(np.max(np.abs(q0 / q_ref - 1.0))),
+                    "window_steps": win, "window_max_rel_err": errs,
+                    "steps_to_5pct": steps_to_converge(tr, q_ref, win, 0.05),
+                    "steps_to_3pct": steps_to_converge(tr, q_ref, win, 0.03),
+                    "seconds_per_step": secs / eval_steps}
     t3 = time.time()
     for _ in range(100):
         sur.predict(x5[None, :])

@@ -36,8 +36,9 @@ def _systems():
     return out
 
 
-def _run_single(B, w, steps):
+def _run_single(B, w, steps, nsplit=1):
     with B.System(w) as s:
+        s.set_pair_split(nsplit)
         s.step(steps)
         x, v, q, st = s.get_state()
         return x, v, q, s.forces(0), st
