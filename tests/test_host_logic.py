@@ -1,0 +1,79 @@
+"""CPU tests of host-side logic: the memory-counter summariser, the surrogate's
+chain geometry and target normalisation, and the input box/fallback rule."""
+import csv
+import math
+
+import numpy as np
+import pytest
+
+from paper_2205_06557_amd import pmc_summary as P
+from paper_2205_06557_amd import surrogate as S
+from paper_2205_06557_amd import workloads as W
+
+
+def _write_counters(path, rows):
+    cols = ["Correlation_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=cols)
+        w.writeheader()
+        for i, (k, c, v) in enumerate(rows):
+            w.writerow({"Correlation_Id": i, "Kernel_Name": k, "Counter_Name": c, "Counter_Value": v})
+
+
+def test_pmc_summary_calibrates_with_the_copy(tmp_path):
+    f = tmp_path / "f.csv"
+    w = tmp_path / "w.csv"
+    # the counter reads half the bytes for reads, all of them for writes
+    _write_counters(f, [("__amd_rocclr_copyBuffer", "FETCH_SIZE", 131072.0),
+                        ("__amd_rocclr_copyBuffer", "FETCH_SIZE", 8.0),
+                        ("void odk::push_kernel<float>(...)", "FETCH_SIZE", 1000.0),
+                        ("void odk::push_kernel<float>(...)", "FETCH_SIZE", 1200.0),
+                        ("void odk::pair_forces_f32<256, 256>(...)", "FETCH_SIZE", 50.0)])
+    _write_counters(w, [("__amd_rocclr_copyBuffer", "WRITE_SIZE", 262144.0),
+                        ("void odk::push_kernel<float>(...)", "WRITE_SIZE", 512.0)])
+    s = P.summarise(str(f), str(w), 1024)
+    assert s["calibration"]["fetch_factor"] == pytest.approx(0.5)
+    assert s["calibration"]["write_factor"] == pytest.approx(1.0)
+    push = s["kernels"]["push"]
+    assert push["fetch_bytes"] == pytest.approx(1100.0 * 1024 / 0.5)
+    assert push["write_bytes"] == pytest.approx(512.0 * 1024)
+    assert s["kernels"]["pair"]["write_bytes"] == 0.0
+    assert len(s["source_sha256"]) == 64
+
+
+def test_chain_geometry():
+    x5 = [1.2, 6.0, 0.5, 0.1, 40.0]
+    w = S.chain_workload(x5, 4096, 6000, 1, 3)
+    lam = w.lam
+    z = [d[2] / lam for d in w.dust]
+    assert len(z) == 8
+    assert np.allclose(np.diff(z), 0.5)
+    assert z[0] == pytest.approx(-1.75)
+    assert w.H / lam == pytest.approx(7 * 0.5 + 5)
+    assert w.R / lam == pytest.approx(3.0)
+    assert w.Te / w.Ti == pytest.approx(40.0)
+    assert w.nu_in / w.wpi == pytest.approx(0.1)
+    assert w.dt * w.wpi == pytest.approx(S.DT_WPI)
+    assert w.n_discard == 6000 - S.AVG_STEPS
+    # every grain inside the domain, away from the walls
+    for (_, _, zz, a, _) in w.dust:
+        assert abs(zz) + a < 0.5 * w.H - 2 * lam
+
+
+def test_targets_round_trip():
+    x5 = np.array([0.7, 3.5, 0.8, 0.2, 25.0])
+    q = -np.linspace(3e-16, 9e-16, 8)
+    f = np.linspace(-2e-13, 1e-13, 8)
+    t = S.to_targets(x5, q, f)
+    q2, f2 = S.from_targets(x5, t)
+    assert np.allclose(q2, q, rtol=1e-14) and np.allclose(f2, f, rtol=1e-14)
+    # the charge scale is the grain capacitance times k_B T_e / e
+    cap = 4 * math.pi * W.EPS0 * 3.5e-6
+    assert S.charge_scale(x5) == pytest.approx(cap * 1.0, rel=1e-12)
+
+
+def test_sweep_inputs_inside_box_and_seeded():
+    X = S.sweep_inputs(500, 7)
+    assert (X >= S.BOX_LO).all() and (X <= S.BOX_HI).all()
+    assert np.array_equal(X, S.sweep_inputs(500, 7))
+    assert not np.array_equal(X, S.sweep_inputs(500, 8))
