@@ -47,6 +47,9 @@
 /* flags */
 #define ORC_F_LITERAL_SIDE 1u   /* side injection: radial + v_z only (Eqs. B.10-B.11 literally) */
 #define ORC_F_NO_ION_ION   2u   /* test-particle mode: ion-ion force off */
+#define ORC_F_CONFINEMENT  4u   /* confinement field of the outer plasma (Appendix A); the
+                                   driver fits it after orc_init and installs it with
+                                   orc_set_confinement */
 
 /* event codes per ion for the last step */
 #define ORC_EV_NONE   (-1)
@@ -79,7 +82,40 @@ typedef struct orc_sys {
     double sumQ[ORC_MAXD], sumF[ORC_MAXD][4][3];
     int64_t nrec;
     int status;
+    /* confinement field of the outer plasma (Appendix A): fitted polynomial
+     * P(r, z) = sum_m alpha_m (r/rs)^(2 a_m) (z/zs)^(2 b_m), in volts */
+    int conf_on;
+    double conf_alpha[15], conf_rs, conf_zs;
 } orc_sys;
+
+/* Exponent pairs (a, b) of the fifteen terms r^(2a) z^(2b) of Eq. (A.3), in
+ * the order alpha_0 .. alpha_14. */
+static const int ORC_PA[15] = {0, 1, 0, 1, 2, 0, 2, 1, 3, 0, 2, 3, 1, 4, 0};
+static const int ORC_PB[15] = {0, 0, 1, 1, 0, 2, 1, 2, 0, 3, 2, 1, 3, 0, 4};
+
+static double orc_ipow(double x, int k)
+{
+    double r = 1.0;
+    for (int i = 0; i < k; ++i) r *= x;
+    return r;
+}
+
+/* Confinement field E_out = -grad P (Eq. (A.4)) at x (SI, V/m). */
+static void orc_confinement_field(const orc_sys* s, const double x[3], double E[3])
+{
+    double u = (x[0] * x[0] + x[1] * x[1]) / (s->conf_rs * s->conf_rs);
+    double v = x[2] * x[2] / (s->conf_zs * s->conf_zs);
+    double dPdu = 0.0, dPdv = 0.0;   /* derivatives with respect to u and v */
+    for (int m = 0; m < 15; ++m) {
+        int a = ORC_PA[m], b = ORC_PB[m];
+        if (a > 0) dPdu += s->conf_alpha[m] * a * orc_ipow(u, a - 1) * orc_ipow(v, b);
+        if (b > 0) dPdv += s->conf_alpha[m] * b * orc_ipow(u, a) * orc_ipow(v, b - 1);
+    }
+    /* dP/dx = dP/du * 2x/rs^2, dP/dz = dP/dv * 2z/zs^2 */
+    E[0] = -dPdu * 2.0 * x[0] / (s->conf_rs * s->conf_rs);
+    E[1] = -dPdu * 2.0 * x[1] / (s->conf_rs * s->conf_rs);
+    E[2] = -dPdv * 2.0 * x[2] / (s->conf_zs * s->conf_zs);
+}
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x64-10 (Salmon, Moraes, Dror & Shaw, SC'11), written from the
@@ -391,6 +427,11 @@ static void orc_accel_one(const orc_sys* s, int64_t i, double out[3])
         ex += f * dx; ey += f * dy; ez += f * dz;
     }
     ez += s->E;
+    if (s->conf_on) {
+        double Eo[3];
+        orc_confinement_field(s, xi, Eo);
+        ex += Eo[0]; ey += Eo[1]; ez += Eo[2];
+    }
     double qm = ORC_QE / s->mi;
     out[0] = qm * ex; out[1] = qm * ey; out[2] = qm * ez;
 }
@@ -404,8 +445,8 @@ void orc_accel_subset(const orc_sys* s, const int64_t* idx, int64_t n_idx, doubl
 
 /* Forces on the dust grains at the current state.
  *   Eq. (1): F_orbit,d = q Q_d/(4 pi eps0) sum_k (1 + rho/r_De) exp(-rho/r_De)
- *            (r_d - r_k)/rho^3  (the out-of-domain E_out term is not
- *            modelled here);
+ *            (r_d - r_k)/rho^3 + Q_d E_out(r_d), the last term only while a
+ *            confinement field is installed;
  *   Eq. (2): F_dd,d = Q_d/(4 pi eps0) sum_{p != d} Q_p (r_d - r_p)/|r_d - r_p|^3;
  *   Eq. (4): F_ext,d = Q_d E (along z).
  * Out: F[d][0] orbit, F[d][1] dust-dust, F[d][3] external (SI, N).        */
@@ -424,6 +465,11 @@ static void orc_dust_forces(const orc_sys* s, double F[][4][3])
         }
         double c = k * s->q * s->Q[d];
         F[d][0][0] = c * sx; F[d][0][1] = c * sy; F[d][0][2] = c * sz;
+        if (s->conf_on) {
+            double Eo[3];
+            orc_confinement_field(s, s->dpos[d], Eo);
+            for (int a = 0; a < 3; ++a) F[d][0][a] += s->Q[d] * Eo[a];
+        }
         double px = 0.0, py = 0.0, pz = 0.0;
         for (int p = 0; p < s->nd; ++p) {
             if (p == d) continue;
@@ -722,6 +768,71 @@ void orc_dust_forces_now(const orc_sys* s, double* F /*[nd][4][3]*/)
     memset(tmp, 0, sizeof tmp);
     orc_dust_forces(s, tmp);
     memcpy(F, tmp, (size_t)s->nd * 12 * sizeof(double));
+}
+
+/* ------------------------------------------------------------------------ */
+/* Confinement field of the outer plasma (Appendix A).
+ *
+ * Eqs. (A.1)-(A.2): the potential inside the cylindrical cavity is the
+ * potential Phi0 of an infinite homogeneous ion background with Yukawa
+ * screening, minus the screened Coulomb potential of the ions that fill the
+ * cavity.  Reading: the ions of the sum are the superparticles at the time
+ * of the call (the driver calls it once, right after orc_init); Phi0 is the
+ * screened potential of the infinite background, n e r_De^2 / eps0 (that
+ * is, k_B T_e / e).  Nodes r_k = k R / nx, z_p = p (H/2) / nz on the
+ * half-plane y = 0, k = 0..nx, p = 0..nz; out[(nz+1) k + p] in volts.  An
+ * ion exactly on a node is left out of that node's sum. */
+void orc_confinement_grid(const orc_sys* s, int nx, int nz, double* out)
+{
+    const double k = 1.0 / (4.0 * ORC_PI * ORC_EPS0);
+    const double phi0 = s->n * ORC_QE * s->lam * s->lam / ORC_EPS0;
+    const int nn = (nx + 1) * (nz + 1);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int g = 0; g < nn; ++g) {
+        const double gx = s->R * (double)(g / (nz + 1)) / (double)nx;
+        const double gz = 0.5 * s->H * (double)(g % (nz + 1)) / (double)nz;
+        double sum = 0.0;
+        for (int64_t l = 0; l < s->N; ++l) {
+            double dx = s->x[3 * l + 0] - gx;
+            double dy = s->x[3 * l + 1];
+            double dz = s->x[3 * l + 2] - gz;
+            double d = sqrt(dx * dx + dy * dy + dz * dz);
+            if (d > 0.0) sum += exp(-d / s->lam) / d;
+        }
+        out[g] = phi0 - k * s->q * sum;
+    }
+}
+
+/* Installs the fitted polynomial of Eq. (A.3), written in the scaled
+ * variables (r/rs)^2 and (z/zs)^2: alpha[m] (volts) multiplies
+ * (r/rs)^(2a_m) (z/zs)^(2b_m).  on = 0 removes the field. */
+void orc_set_confinement(orc_sys* s, const double* alpha, double rs, double zs, int on)
+{
+    for (int m = 0; m < 15; ++m) s->conf_alpha[m] = alpha[m];
+    s->conf_rs = rs;
+    s->conf_zs = zs;
+    s->conf_on = on ? 1 : 0;
+}
+
+/* Exponents (powers of r and of z, as printed in Eq. (A.3)) of the terms. */
+void orc_confinement_terms(int* r_pow, int* z_pow)
+{
+    for (int m = 0; m < 15; ++m) { r_pow[m] = 2 * ORC_PA[m]; z_pow[m] = 2 * ORC_PB[m]; }
+}
+
+/* P (volts) and E_out = -grad P (V/m) at n points x[n][3] (SI). */
+void orc_confinement_eval(const orc_sys* s, int64_t n, const double* x, double* P, double* E)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        const double* xi = x + 3 * i;
+        double u = (xi[0] * xi[0] + xi[1] * xi[1]) / (s->conf_rs * s->conf_rs);
+        double v = xi[2] * xi[2] / (s->conf_zs * s->conf_zs);
+        double p = 0.0;
+        for (int m = 0; m < 15; ++m)
+            p += s->conf_alpha[m] * orc_ipow(u, ORC_PA[m]) * orc_ipow(v, ORC_PB[m]);
+        if (P) P[i] = p;
+        if (E) orc_confinement_field(s, xi, E + 3 * i);
+    }
 }
 
 int orc_num_threads(void)

@@ -25,6 +25,10 @@ LIB = os.path.join(HERE, "libodust_oracle.so")
 
 EV_NONE = -1
 EV_EXITED = -2
+FLAG_CONFINEMENT = 4
+# grid of the confinement potential (Appendix A): intervals along r and along z
+CONF_NX = 32
+CONF_NZ = 32
 
 
 def build(force: bool = False) -> str:
@@ -82,6 +86,10 @@ def lib():
         L.orc_ion_current_oml.argtypes = [C.c_double] * 6
         L.orc_ion_current_oml.restype = C.c_double
         L.orc_num_threads.restype = C.c_int
+        L.orc_confinement_grid.argtypes = [P, C.c_int, C.c_int, dp]
+        L.orc_set_confinement.argtypes = [P, dp, C.c_double, C.c_double, C.c_int]
+        L.orc_confinement_terms.argtypes = [i32p, i32p]
+        L.orc_confinement_eval.argtypes = [P, C.c_int64, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -123,6 +131,29 @@ def ion_current_oml(Q: float, a: float, n: float, Ti: float, mi: float, u: float
     return lib().orc_ion_current_oml(Q, a, n, Ti, mi, u)
 
 
+def confinement_terms():
+    """(powers of r, powers of z) of the fifteen terms of Eq. (A.3), in the
+    order of their coefficients alpha_0 .. alpha_14."""
+    a = np.zeros(15, dtype=np.int32)
+    b = np.zeros(15, dtype=np.int32)
+    i32 = C.POINTER(C.c_int32)
+    lib().orc_confinement_terms(a.ctypes.data_as(i32), b.ctypes.data_as(i32))
+    return a, b
+
+
+def fit_polynomial(grid: np.ndarray, nx: int, nz: int) -> np.ndarray:
+    """Least-squares fit of Eq. (A.3) to the grid of Eq. (A.2), every node
+    weighted alike.  The terms are written in the scaled variables
+    (r/R)^2 = (k/nx)^2 and (z/(H/2))^2 = (p/nz)^2, which spans the same
+    polynomials as the printed form and keeps the system well conditioned;
+    coefficient m multiplies (r/R)^(r_pow_m) (z/(H/2))^(z_pow_m)."""
+    rp, zp = confinement_terms()
+    k, p = np.meshgrid(np.arange(nx + 1) / nx, np.arange(nz + 1) / nz, indexing="ij")
+    A = np.stack([k.ravel() ** a * p.ravel() ** b for a, b in zip(rp, zp)], axis=1)
+    alpha, *_ = np.linalg.lstsq(A, np.asarray(grid, dtype=np.float64).ravel(), rcond=None)
+    return alpha
+
+
 def num_threads() -> int:
     return lib().orc_num_threads()
 
@@ -150,10 +181,14 @@ class Oracle:
         L.orc_derived(self._h, _dp(d), t.ctypes.data_as(C.POINTER(C.c_uint64)))
         self.derived = dict(zip(self.DERIVED, d.tolist()))
         self.Tc, self.Tb, self.Tbt = (int(x) for x in t)
+        self.conf_alpha = None
+        self.conf_grid = None
         if init:
             st = L.orc_init(self._h)
             if st != 0:
                 raise RuntimeError(f"oracle init failed ({st})")
+            if int(w.flags) & FLAG_CONFINEMENT:
+                self.fit_confinement()
 
     def __del__(self):
         if getattr(self, "_h", None):
@@ -213,6 +248,36 @@ class Oracle:
         a = np.zeros((len(idx), 3))
         lib().orc_accel_subset(self._h, idx.ctypes.data_as(C.POINTER(C.c_int64)), len(idx), _dp(a))
         return a
+
+    # --- confinement field (Appendix A) ---------------------------------
+    def confinement_grid(self, nx: int = CONF_NX, nz: int = CONF_NZ) -> np.ndarray:
+        """Phi_ext of Eq. (A.1) at the nodes of Eq. (A.2) from the current ion
+        positions, volts, shape [nx+1, nz+1] (index k along r, p along z)."""
+        out = np.zeros((nx + 1) * (nz + 1))
+        lib().orc_confinement_grid(self._h, nx, nz, _dp(out))
+        return out.reshape(nx + 1, nz + 1)
+
+    def fit_confinement(self, nx: int = CONF_NX, nz: int = CONF_NZ) -> np.ndarray:
+        """Computes the grid from the current positions, fits Eq. (A.3) by
+        least squares and installs the field.  Returns the coefficients."""
+        grid = self.confinement_grid(nx, nz)
+        rs, zs = self.w.R, 0.5 * self.w.H
+        alpha = fit_polynomial(grid, nx, nz)
+        lib().orc_set_confinement(self._h, _dp(alpha), rs, zs, 1)
+        self.conf_grid, self.conf_alpha = grid, alpha
+        return alpha
+
+    def set_confinement(self, alpha, on: bool = True):
+        a = np.ascontiguousarray(alpha, dtype=np.float64)
+        lib().orc_set_confinement(self._h, _dp(a), self.w.R, 0.5 * self.w.H, int(on))
+
+    def confinement_eval(self, x):
+        """(P [n] volts, E_out [n,3] V/m) of the installed polynomial at x [n,3] (m)."""
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 3)
+        P = np.zeros(len(x))
+        E = np.zeros((len(x), 3))
+        lib().orc_confinement_eval(self._h, len(x), _dp(x), _dp(P), _dp(E))
+        return P, E
 
     def dust_forces(self) -> np.ndarray:
         F = np.zeros((max(self.nd, 1), 4, 3))
