@@ -57,6 +57,10 @@ typedef enum {
                                     (Eqs. B.10-B.11 as printed); default adds the
                                     tangential thermal component Eq. (B.1) implies */
 #define OD_FLAG_NO_ION_ION 2u    /* test-particle mode: ion-ion force switched off */
+#define OD_FLAG_CONFINEMENT 4u   /* confinement field of the plasma outside the domain
+                                    (Appendix A): computed once, from the ions placed by
+                                    initialisation, and added to every ion's acceleration
+                                    and, as Q_d E_out, to the force of Eq. (1) */
 
 /* od_sim.precision */
 #define OD_PREC_FP32 0           /* FP32 state and pair tiles, FP64 charge/force sums */
@@ -155,6 +159,23 @@ const char* od_last_error(void);
  * acceleration r_De omega_pi^2 (m/s^2)}. */
 od_status od_get_units(od_system* sys, double* units_host);
 
+/* Confinement field of a system created with OD_FLAG_CONFINEMENT (Appendix A).
+ * At creation the potential of Eq. (A.1) -- the screened potential
+ * k_B T_e / e of an infinite homogeneous ion background minus the screened
+ * Coulomb potential of the initial ions -- is computed on the grid of
+ * Eq. (A.2), nodes (k R / nr, 0, p (H/2) / nz) for k = 0..nr, p = 0..nz
+ * (nr = nz = 32), and fitted by least squares, every node weighted alike,
+ * with the fifteen terms of Eq. (A.3) written in r/R and z/(H/2):
+ * coef_host[m] (volts) multiplies (r/R)^(2 a_m) (z/(H/2))^(2 b_m), (a_m, b_m)
+ * = (0,0) (1,0) (0,1) (1,1) (2,0) (0,2) (2,1) (1,2) (3,0) (0,3) (2,2) (3,1)
+ * (1,3) (4,0) (0,4).  The field E_out = -grad P (Eq. (A.4)) stays fixed for
+ * the life of the system (od_set_state does not refit it).
+ * grid_host[(nz + 1) k + p] receives the grid potentials in volts
+ * ((nr + 1)(nz + 1) doubles); coef_host, grid_host, nr, nz may be NULL.
+ * OD_ESTATE if the system was created without the flag. */
+od_status od_get_confinement(od_system* sys, double* coef_host, double* grid_host, int32_t* nr,
+                             int32_t* nz);
+
 /* Sizes: out_host[4] = {N, n_dust, precision, padded N}. */
 od_status od_get_sizes(od_system* sys, int64_t* out_host);
 
@@ -252,6 +273,9 @@ od_status od_batch_get_state(od_batch* b, int32_t system, float* x_host, float* 
 od_status od_batch_set_state(od_batch* b, int32_t system, const float* x_host, const float* v_host,
                              const double* q_host, int64_t step);
 od_status od_batch_get_accelerations(od_batch* b, int32_t system, float* a_host);
+/* As od_get_confinement, for one member of the batch. */
+od_status od_batch_get_confinement(od_batch* b, int32_t system, double* coef_host, double* grid_host,
+                                   int32_t* nr, int32_t* nz);
 od_status od_batch_get_step_events(od_batch* b, int32_t system, uint8_t* ev_host, int64_t* n_abs_host,
                                    int64_t* n_exit, int64_t* n_coll);
 

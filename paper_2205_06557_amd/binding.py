@@ -94,10 +94,13 @@ def lib():
         L.od_rng_block.argtypes = [u64, u64, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
         L.od_set_timing.argtypes = [vp, C.c_int32]
         L.od_get_kernel_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.od_get_confinement.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                         C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         for name in ("od_init_system", "od_step", "od_sync", "od_get_dust_charges",
                      "od_get_dust_forces", "od_get_units", "od_get_sizes", "od_get_state",
                      "od_set_state", "od_get_accelerations", "od_get_step_events",
-                     "od_rng_block", "od_set_timing", "od_get_kernel_times"):
+                     "od_rng_block", "od_set_timing", "od_get_kernel_times",
+                     "od_get_confinement"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -150,6 +153,15 @@ def rng_block(seed: int, system: int, ctr) -> np.ndarray:
     out = np.zeros(4, dtype=np.uint64)
     _check(lib().od_rng_block(seed, system, _ptr(c, C.c_uint64), _ptr(out, C.c_uint64)))
     return out
+
+
+def _confinement(call):
+    nr, nz = C.c_int32(0), C.c_int32(0)
+    _check(call(None, None, C.byref(nr), C.byref(nz)))
+    coef = np.zeros(15)
+    grid = np.zeros((nr.value + 1) * (nz.value + 1))
+    _check(call(_ptr(coef), _ptr(grid), C.byref(nr), C.byref(nz)))
+    return coef, grid.reshape(nr.value + 1, nz.value + 1)
 
 
 class System:
@@ -234,6 +246,11 @@ class System:
         _check(lib().od_get_accelerations(self._h, a.ctypes.data))
         return a
 
+    def confinement(self):
+        """(coefficients [15] in volts, grid [nr+1, nz+1] in volts) of the
+        confinement field fitted at creation."""
+        return _confinement(lambda *a: lib().od_get_confinement(self._h, *a))
+
     def events(self):
         ev = np.zeros(self.N, dtype=np.uint8)
         nabs = np.zeros(max(self.nd, 1), dtype=np.int64)
@@ -283,11 +300,13 @@ def _batch_lib():
         L.od_batch_get_step_events.argtypes = [vp, i32, C.POINTER(C.c_uint8), i64p, i64p, i64p]
         L.od_batch_set_timing.argtypes = [vp, i32]
         L.od_batch_get_kernel_times.argtypes = [vp, dp, i64p]
+        L.od_batch_get_confinement.argtypes = [vp, i32, dp, dp, C.POINTER(C.c_int32),
+                                               C.POINTER(C.c_int32)]
         for name in ("od_init_batch", "od_batch_set_config", "od_batch_get_config", "od_batch_autotune",
                      "od_batch_set_graph", "od_step_batch", "od_batch_sync", "od_batch_get_sizes",
                      "od_batch_get_dust_charges", "od_batch_get_dust_forces", "od_batch_get_state",
                      "od_batch_set_state", "od_batch_get_accelerations", "od_batch_get_step_events",
-                     "od_batch_set_timing", "od_batch_get_kernel_times"):
+                     "od_batch_set_timing", "od_batch_get_kernel_times", "od_batch_get_confinement"):
             getattr(L, name).restype = C.c_int
         _batch_sigs = True
     return L
@@ -399,6 +418,9 @@ class Batch:
         _check(_batch_lib().od_batch_get_accelerations(self._h, s, a.ctypes.data))
         return a
 
+    def confinement(self, s: int):
+        return _confinement(lambda *a: _batch_lib().od_batch_get_confinement(self._h, s, *a))
+
     def events(self, s: int):
         N = int(self.ws[s].n_ions)
         ev = np.zeros(N, dtype=np.uint8)
@@ -441,6 +463,9 @@ class BatchMember:
 
     def accelerations(self):
         return self.b.accelerations(self.s)
+
+    def confinement(self):
+        return self.b.confinement(self.s)
 
     def events(self):
         return self.b.events(self.s)

@@ -15,6 +15,8 @@
 //       time averages, clearing of the accumulators, step counter.
 //   init_kernel<T>      initial uniform positions and shifted-Maxwellian
 //       velocities.
+//   conf_grid_kernel<T> potential of the plasma outside the domain on the
+//       (r, z) grid of Appendix A, from the ions at the time of the call.
 //
 // Dimensionless units: length r_De, time 1/omega_pi, velocity c_s, charge e.
 #pragma once
@@ -30,6 +32,38 @@ struct DustSet {
     double rad2[kMaxDust];
 };
 
+// Confinement field of the plasma outside the domain (Appendix A), in
+// dimensionless form: potential in k_B T_e / e and lengths in r_De, so that
+// the field is the ion's dimensionless acceleration.  The fitted potential is
+// P = sum_m c[m] u^a_m v^b_m with u = (x^2 + y^2) iu, v = z^2 iv, the terms in
+// the order of Eq. (A.3): (a, b) = (0,0) (1,0) (0,1) (1,1) (2,0) (0,2) (2,1)
+// (1,2) (3,0) (0,3) (2,2) (3,1) (1,3) (4,0) (0,4).
+struct ConfField {
+    int on, pad_;
+    double c[15];
+    double iu, iv;      // 1 / rs^2, 1 / zs^2 (rs = R, zs = H / 2)
+};
+
+// E = -grad P at (x, y, z), Eq. (A.4); the u and v derivatives written out
+// term by term.
+__host__ __device__ inline void conf_field(const ConfField& f, double x, double y, double z,
+                                           double& ex, double& ey, double& ez)
+{
+    const double* c = f.c;
+    const double u = (x * x + y * y) * f.iu, v = z * z * f.iv;
+    const double u2 = u * u, v2 = v * v;
+    const double dPu = c[1] + c[3] * v + 2.0 * c[4] * u + 2.0 * c[6] * u * v + c[7] * v2 +
+                       3.0 * c[8] * u2 + 2.0 * c[10] * u * v2 + 3.0 * c[11] * u2 * v +
+                       c[12] * v2 * v + 4.0 * c[13] * u2 * u;
+    const double dPv = c[2] + c[3] * u + 2.0 * c[5] * v + c[6] * u2 + 2.0 * c[7] * u * v +
+                       3.0 * c[9] * v2 + 2.0 * c[10] * u2 * v + c[11] * u2 * u +
+                       3.0 * c[12] * u * v2 + 4.0 * c[14] * v2 * v;
+    const double gu = -2.0 * dPu * f.iu;
+    ex = gu * x;
+    ey = gu * y;
+    ez = -2.0 * dPv * f.iv * z;
+}
+
 struct PairArgs {
     int N, Npad, nd, ion_ion;
     float C;        // ion-ion coupling: (superparticle weight)/(4 pi n r_De^3) = V/(4 pi N)
@@ -37,6 +71,7 @@ struct PairArgs {
     double Cd;      // same in FP64
     double Kq;      // ion<-grain coupling per unit grain charge (e): 1/(4 pi n r_De^3)
     double Ez;      // homogeneous drive along z (dimensionless acceleration)
+    ConfField cf;   // confinement field, added to every ion when cf.on
 };
 
 struct PushArgs {
@@ -59,6 +94,7 @@ struct FinalArgs {
     double c_dd;                    // N per e^2 per dimensionless 1/r^2
     double c_coll;                  // N per (dimensionless velocity sum)
     double c_ext;                   // N per e (e * E_SI)
+    double eout[kMaxDust][3];       // N per e: e * E_out(r_d) of the confinement field, or 0
 };
 
 // ---------------------------------------------------------------------------
@@ -137,6 +173,11 @@ __device__ __forceinline__ void pair_block_f32(const float* __restrict__ X,
         // grain terms in FP64 (N_d per ion) and the drive
         const double xd = xi, yd = yi, zd = zi;
         gz += p.Ez;
+        if (p.cf.on) {
+            double ex, ey, ez;
+            conf_field(p.cf, xd, yd, zd, ex, ey, ez);
+            gx += ex; gy += ey; gz += ez;
+        }
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
         for (int d = 0; d < ds.nd; ++d) {
             const double rx = xd - ds.pos[d][0], ry = yd - ds.pos[d][1], rz = zd - ds.pos[d][2];
@@ -237,6 +278,11 @@ __global__ __launch_bounds__(BLOCK) void pair_forces_f64(const double* __restric
     }
     const bool live = i < p.N;
     double gx = p.Cd * sx, gy = p.Cd * sy, gz = p.Cd * sz + p.Ez;
+    if (p.cf.on) {
+        double ex, ey, ez;
+        conf_field(p.cf, xi, yi, zi, ex, ey, ez);
+        gx += ex; gy += ey; gz += ez;
+    }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int d = 0; d < ds.nd; ++d) {
         const double rx = xi - ds.pos[d][0], ry = yi - ds.pos[d][1], rz = zi - ds.pos[d][2];
@@ -561,7 +607,9 @@ __device__ __forceinline__ void finalize_sys(const FinalArgs& f, const DustSet& 
         // forces, SI
         double F[12];
         const double co = f.c_orbit * Qn;
-        F[0] = co * S0; F[1] = co * S1; F[2] = co * S2;
+        F[0] = co * S0 + Qn * f.eout[d][0];
+        F[1] = co * S1 + Qn * f.eout[d][1];
+        F[2] = co * S2 + Qn * f.eout[d][2];
         double px = 0.0, py = 0.0, pz = 0.0;
         for (int q = 0; q < f.nd; ++q) {
             if (q == d) continue;
@@ -663,6 +711,35 @@ __global__ __launch_bounds__(256) void init_kernel(T* __restrict__ xs, T* __rest
     if (i >= Npad) return;
     init_ion<T>(xs, xs + Npad, xs + 2 * Npad, vs, vs + Npad, vs + 2 * Npad, i, p, ds, ctl);
     as[i] = 0; as[Npad + i] = 0; as[2 * Npad + i] = 0;
+}
+
+// Confinement potential (Appendix A, Eqs. (A.1)-(A.2)), dimensionless:
+// out[(nz + 1) k + p] = 1 - C sum_l exp(-d_l) / d_l at the node
+// (k R / nx, 0, p (H/2) / nz), the sum over the N ions of one system at
+// X, Y, Z; 1 is the screened potential of the infinite background and C the
+// ion-ion coupling.  One block per node; an ion exactly on a node is left
+// out.  Grid: (nx + 1) (nz + 1) blocks of 256.
+template <typename T>
+__global__ __launch_bounds__(256) void conf_grid_kernel(const T* __restrict__ X,
+                                                        const T* __restrict__ Y,
+                                                        const T* __restrict__ Z, int N, double C,
+                                                        double R, double Hh, int nx, int nz,
+                                                        double* __restrict__ out)
+{
+    __shared__ double part[4];
+    const int g = blockIdx.x;
+    const double gx = R * (double)(g / (nz + 1)) / (double)nx;
+    const double gz = Hh * (double)(g % (nz + 1)) / (double)nz;
+    double s = 0.0;
+    for (int l = threadIdx.x; l < N; l += 256) {
+        const double dx = (double)X[l] - gx, dy = (double)Y[l], dz = (double)Z[l] - gz;
+        const double d = sqrt(dx * dx + dy * dy + dz * dz);
+        s += d > 0.0 ? exp(-d) / d : 0.0;
+    }
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[g] = 1.0 - C * (((part[0] + part[1]) + part[2]) + part[3]);
 }
 
 __global__ void rng_kernel(uint64_t k0, uint64_t k1, uint64_t c0, uint64_t c1, uint64_t c2,

@@ -38,6 +38,8 @@ constexpr int kPairTile = 256;
 constexpr int kPad = 256;
 constexpr int kReinjGrid = 2 * odk::kSlots;   // a multiple of the lost-list segments
 constexpr int kMaxSplitSingle = 4;             // source splits of one system's pair sum
+constexpr int kConfNr = 32, kConfNz = 32;      // intervals of the confinement grid along r, z
+constexpr int kConfNodes = (kConfNr + 1) * (kConfNz + 1);
 
 thread_local std::string g_err;
 
@@ -98,6 +100,7 @@ struct od_system {
     odk::PairArgs pa{};
     odk::PushArgs pu{};
     odk::FinalArgs fa{};
+    std::vector<double> conf_grid;      // dimensionless confinement potentials
     // device memory
     void* x = nullptr;
     void* v = nullptr;
@@ -148,7 +151,8 @@ od_status check_params(const od_plasma* pl, const od_sim* sim, const od_dust* du
     if (sim->charge_mode < 0 || sim->charge_mode > 2) return fail(OD_EINVAL, "bad charge_mode");
     if (sim->precision != OD_PREC_FP32 && sim->precision != OD_PREC_FP64)
         return fail(OD_EINVAL, "bad precision");
-    if (sim->flags & ~(OD_FLAG_LITERAL_SIDE | OD_FLAG_NO_ION_ION)) return fail(OD_EINVAL, "unknown flags");
+    if (sim->flags & ~(OD_FLAG_LITERAL_SIDE | OD_FLAG_NO_ION_ION | OD_FLAG_CONFINEMENT))
+        return fail(OD_EINVAL, "unknown flags");
     if (sim->reserved != 0) return fail(OD_EINVAL, "reserved must be 0");
     for (int d = 0; d < nd; ++d) {
         const od_dust& g = dust[d];
@@ -257,6 +261,102 @@ void derive_consts(const od_plasma& P, const od_sim& S, const od_dust* dust, int
     fa.c_dd = k_e2;
     fa.c_coll = w * P.m_i * cs / S.dt;
     fa.c_ext = kQE * E_si;
+}
+
+// Exponents of u = (r/R)^2 and v = (z/(H/2))^2 in the fifteen terms of
+// Eq. (A.3), in the order of the coefficients alpha_0 .. alpha_14.
+constexpr int kTermU[15] = {0, 1, 0, 1, 2, 0, 2, 1, 3, 0, 2, 3, 1, 4, 0};
+constexpr int kTermV[15] = {0, 0, 1, 1, 0, 2, 1, 2, 0, 3, 2, 1, 3, 0, 4};
+
+double ipow(double x, int k)
+{
+    double r = 1.0;
+    while (k-- > 0) r *= x;
+    return r;
+}
+
+// Least-squares fit of Eq. (A.3) to the confinement grid (node (k, p) at
+// index (kConfNz + 1) k + p), every node weighted alike: Householder QR of
+// the (nodes x 15) design matrix in the scaled variables u = (k/nr)^2,
+// v = (p/nz)^2, then back substitution.  False if the matrix is singular.
+bool fit_confinement(const double* grid, double* coef)
+{
+    const int m = kConfNodes, n = 15;
+    std::vector<double> A((size_t)m * n), b(grid, grid + m), rdiag(n);   // A column-major
+    for (int g = 0; g < m; ++g) {
+        const double r = (double)(g / (kConfNz + 1)) / kConfNr, z = (double)(g % (kConfNz + 1)) / kConfNz;
+        for (int j = 0; j < n; ++j) A[(size_t)j * m + g] = ipow(r * r, kTermU[j]) * ipow(z * z, kTermV[j]);
+    }
+    for (int j = 0; j < n; ++j) {
+        double* a = &A[(size_t)j * m];
+        double nrm = 0.0;
+        for (int i = j; i < m; ++i) nrm += a[i] * a[i];
+        nrm = std::sqrt(nrm);
+        if (!(nrm > 0.0)) return false;
+        const double alpha = a[j] > 0.0 ? -nrm : nrm;
+        a[j] -= alpha;                                  // Householder vector in a[j..m)
+        double vv = 0.0;
+        for (int i = j; i < m; ++i) vv += a[i] * a[i];
+        auto reflect = [&](double* col) {
+            double dot = 0.0;
+            for (int i = j; i < m; ++i) dot += a[i] * col[i];
+            const double f = 2.0 * dot / vv;
+            for (int i = j; i < m; ++i) col[i] -= f * a[i];
+        };
+        for (int k = j + 1; k < n; ++k) reflect(&A[(size_t)k * m]);
+        reflect(b.data());
+        rdiag[j] = alpha;
+    }
+    for (int j = n - 1; j >= 0; --j) {
+        double t = b[j];
+        for (int k = j + 1; k < n; ++k) t -= A[(size_t)k * m + j] * coef[k];
+        coef[j] = t / rdiag[j];
+        if (!std::isfinite(coef[j])) return false;
+    }
+    return true;
+}
+
+// Confinement field of one system (Appendix A), from its ions at X, Y, Z:
+// the grid on the device into dbuf (kConfNodes doubles), the fit on the host.
+// Fills grid (dimensionless potentials), the field of the pair kernels and
+// e E_out at every grain for the force of Eq. (1).  Synchronises the stream.
+template <typename T>
+od_status setup_confinement(hipStream_t st, const T* X, const T* Y, const T* Z, int N,
+                            double* dbuf, SysConsts& c, double Te, std::vector<double>& grid)
+{
+    const double R = c.pu.R, Hh = 0.5 * c.pu.H;
+    odk::conf_grid_kernel<T><<<kConfNodes, 256, 0, st>>>(X, Y, Z, N, c.pa.Cd, R, Hh, kConfNr, kConfNz, dbuf);
+    HIPCHK(hipGetLastError());
+    grid.assign(kConfNodes, 0.0);
+    HIPCHK(hipMemcpyAsync(grid.data(), dbuf, kConfNodes * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    odk::ConfField& cf = c.pa.cf;
+    if (!fit_confinement(grid.data(), cf.c)) return fail(OD_ENUMERIC, "confinement fit failed");
+    cf.on = 1;
+    cf.iu = 1.0 / (R * R);
+    cf.iv = 1.0 / (Hh * Hh);
+    const double e_unit = kKB * Te / c.lam;          // N per e per unit dimensionless field
+    for (int d = 0; d < c.ds.nd; ++d) {
+        double e[3];
+        odk::conf_field(cf, c.ds.pos[d][0], c.ds.pos[d][1], c.ds.pos[d][2], e[0], e[1], e[2]);
+        for (int k = 0; k < 3; ++k) c.fa.eout[d][k] = e[k] * e_unit;
+    }
+    return OD_OK;
+}
+
+// Coefficients (volts) and grid (volts, may be null) of a fitted field.
+od_status report_confinement(const odk::ConfField& cf, const std::vector<double>& grid, double Te,
+                             double* coef, double* grid_out, int32_t* nr, int32_t* nz)
+{
+    if (!cf.on) return fail(OD_ESTATE, "the confinement field is not enabled for this system");
+    const double volt = kKB * Te / kQE;
+    if (coef)
+        for (int m = 0; m < 15; ++m) coef[m] = cf.c[m] * volt;
+    if (grid_out)
+        for (int g = 0; g < kConfNodes; ++g) grid_out[g] = grid[g] * volt;
+    if (nr) *nr = kConfNr;
+    if (nz) *nz = kConfNz;
+    return OD_OK;
 }
 
 void derive(od_system* s)
@@ -422,6 +522,26 @@ od_status od_init_system(const od_plasma* plasma, const od_sim* sim, const od_du
         return fail(OD_EDEVICE, "init kernel launch failed: %s", hipGetErrorString(e));
     }
     st = read_status(s);
+    if (st == OD_OK && (sim->flags & OD_FLAG_CONFINEMENT)) {
+        double* dbuf = (double*)dev_alloc(s, kConfNodes * sizeof(double));
+        if (!dbuf) st = fail(OD_ENOMEM, "device allocation of the confinement grid failed");
+        SysConsts c;
+        c.lam = s->lam; c.ds = s->ds; c.pa = s->pa; c.pu = s->pu; c.fa = s->fa;
+        const int64_t P = s->Npad;
+        if (st == OD_OK && s->prec == OD_PREC_FP32) {
+            const float* x = (const float*)s->x;
+            st = setup_confinement<float>(s->stream, x, x + P, x + 2 * P, (int)s->N, dbuf, c, plasma->T_e, s->conf_grid);
+        } else if (st == OD_OK) {
+            const double* x = (const double*)s->x;
+            st = setup_confinement<double>(s->stream, x, x + P, x + 2 * P, (int)s->N, dbuf, c, plasma->T_e, s->conf_grid);
+        }
+        if (dbuf) {
+            (void)hipStreamSynchronize(s->stream);
+            dev_free(s, dbuf);
+        }
+        s->pa = c.pa;
+        s->fa = c.fa;
+    }
     if (st != OD_OK) {
         od_destroy(s);
         return st;
@@ -489,6 +609,12 @@ void od_destroy(od_system* s)
     dev_free(s, s->ctl);
     for (hipEvent_t e : s->evpool) (void)hipEventDestroy(e);
     delete s;
+}
+
+od_status od_get_confinement(od_system* s, double* coef, double* grid, int32_t* nr, int32_t* nz)
+{
+    if (!s) return fail(OD_EINVAL, "null system");
+    return report_confinement(s->pa.cf, s->conf_grid, s->pl.T_e, coef, grid, nr, nz);
 }
 
 od_status od_get_units(od_system* s, double* u)
