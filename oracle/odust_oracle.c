@@ -47,6 +47,9 @@
 /* flags */
 #define ORC_F_LITERAL_SIDE 1u   /* side injection: radial + v_z only (Eqs. B.10-B.11 literally) */
 #define ORC_F_NO_ION_ION   2u   /* test-particle mode: ion-ion force off */
+#define ORC_F_FIELD_DRIVEN 8u   /* field-driven collisional flow: injection and initial v_z
+                                   from the stationary distribution of the drift between
+                                   charge-exchange collisions (needs nu > 0) */
 #define ORC_F_CONFINEMENT  4u   /* confinement field of the outer plasma (Appendix A); the
                                    driver fits it after orc_init and installs it with
                                    orc_set_confinement */
@@ -65,6 +68,7 @@ typedef struct orc_sys {
     double dpos[ORC_MAXD][3], da[ORC_MAXD], dq0[ORC_MAXD];
     /* derived */
     double lam, wpi, cs, sig, u, V, w, q, m, E, Pc;
+    double ufd;             /* field-driven flow: mean drift gained between collisions, eE/(m nu) */
     double Jb, Jt, Js;
     uint64_t Tc, Tb, Tbt;
     /* state */
@@ -221,6 +225,56 @@ double orc_flux_inverse(double uu, double ubar, double sig)
     return v;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Field-driven collisional flow (Section 2: homogeneous driving field,
+ * charge exchange at constant frequency nu that restarts an ion from the
+ * neutrals' Maxwellian).  Between collisions an ion gains a t along z, and in
+ * a stationary flow the time since the last collision is exponential with
+ * rate nu, so v_z = sig g + ufd T with g ~ N(0,1), T ~ Exp(1), ufd = a/nu:
+ * the Gaussian convolved with an exponential, the phi(v_z) of Eq. (B.1) for
+ * this flow (v_x, v_y stay Maxwellian).  With A(x) = exp(c - x/ufd)
+ * Phi(x/sig - sig/ufd), c = sig^2/(2 ufd^2):
+ *   phi(x)                         = A(x) / ufd,
+ *   int_x^inf v phi(v) dv          = (x + ufd) A(x) + sig pdf(x/sig) + ufd Phic(x/sig),
+ *   -int_-inf^(-w) v phi(v) dv     = (ufd - w) A(-w) + sig pdf(w/sig) - ufd Phic(w/sig),
+ * obtained by integrating by parts (the exponential factors of A combine
+ * with the Gaussian into pdf(x/sig)).  Valid for sig/ufd up to about 30. */
+static double orc_fd_A(double x, double ufd, double sig)
+{
+    double c = 0.5 * sig * sig / (ufd * ufd);
+    return exp(c - x / ufd) * orc_Phi(x / sig - sig / ufd);
+}
+
+double orc_fd_density(double x, double ufd, double sig) { return orc_fd_A(x, ufd, sig) / ufd; }
+
+/* int_x^inf v phi(v) dv; at x = 0 the inflow per unit area of the bottom face */
+double orc_fd_tail(double x, double ufd, double sig)
+{
+    return (x + ufd) * orc_fd_A(x, ufd, sig) + sig * orc_pdf(x / sig) + ufd * orc_Phic(x / sig);
+}
+
+/* -int_-inf^(-w) v phi(v) dv for w >= 0; at w = 0 the inflow of the top face */
+double orc_fd_head(double w, double ufd, double sig)
+{
+    return (ufd - w) * orc_fd_A(-w, ufd, sig) + sig * orc_pdf(w / sig) - ufd * orc_Phic(w / sig);
+}
+
+/* Flux-weighted inward speed at a face (Eqs. (B.8)-(B.9) with the
+ * field-driven phi): the s >= 0 with tail(s) = uu * tail(0), where tail is
+ * orc_fd_tail (bottom, v_z = s) or orc_fd_head (top, v_z = -s).  Bisection
+ * on [0, 40 sig + 50 ufd] to |ds| <= 1e-13 sig. */
+double orc_fd_inverse(double uu, double ufd, double sig, int top)
+{
+    double target = uu * (top ? orc_fd_head(0.0, ufd, sig) : orc_fd_tail(0.0, ufd, sig));
+    double lo = 0.0, hi = 40.0 * sig + (top ? 0.0 : 50.0 * ufd);
+    while (hi - lo > 1e-13 * sig) {
+        double mid = 0.5 * (lo + hi);
+        double t = top ? orc_fd_head(mid, ufd, sig) : orc_fd_tail(mid, ufd, sig);
+        if (t > target) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
 /* OML currents (Section 2, charging models; Allen 1992).
  * Electron current: Boltzmann-repelled random flux for phi < 0, OML-attracted
  * for phi >= 0.  Ion current: OML cross-section pi a^2 (1 - 2 e phi/(m v^2))
@@ -283,8 +337,14 @@ static void orc_derive(orc_sys* s)
         s->E = s->E_in;
     s->Pc = -expm1(-s->nu * s->dt);
     s->Tc = orc_prob_to_u64(s->Pc);
-    s->Jb = ORC_PI * s->R * s->R * orc_face_flux(s->u, s->sig);
-    s->Jt = ORC_PI * s->R * s->R * orc_face_flux(-s->u, s->sig);
+    s->ufd = (s->nu > 0.0) ? ORC_QE * s->E / (s->mi * s->nu) : 0.0;
+    if (s->flags & ORC_F_FIELD_DRIVEN) {
+        s->Jb = ORC_PI * s->R * s->R * orc_fd_tail(0.0, s->ufd, s->sig);
+        s->Jt = ORC_PI * s->R * s->R * orc_fd_head(0.0, s->ufd, s->sig);
+    } else {
+        s->Jb = ORC_PI * s->R * s->R * orc_face_flux(s->u, s->sig);
+        s->Jt = ORC_PI * s->R * s->R * orc_face_flux(-s->u, s->sig);
+    }
     s->Js = 2.0 * ORC_PI * s->R * s->H * s->sig / sqrt(2.0 * ORC_PI);
     double J = s->Jb + s->Jt + s->Js;
     s->Tb = orc_prob_to_u64(s->Jb / J);
@@ -298,6 +358,7 @@ orc_sys* orc_create(const double* plasma /*Te,Ti,n,mi,mach,nu,E*/,
                     int mode, int flags, const double* dust /*[nd][5] x,y,z,a,q0*/, int nd)
 {
     if (N < 1 || nd < 0 || nd > ORC_MAXD) return NULL;
+    if ((flags & ORC_F_FIELD_DRIVEN) && !(plasma[5] > 0.0)) return NULL;
     orc_sys* s = (orc_sys*)calloc(1, sizeof(orc_sys));
     if (!s) return NULL;
     s->Te = plasma[0]; s->Ti = plasma[1]; s->n = plasma[2]; s->mi = plasma[3];
@@ -334,12 +395,12 @@ void orc_destroy(orc_sys* s)
 }
 
 /* Derived constants, for tests: lam, wpi, cs, sig, u, V, w, q, m, E, Pc,
- * Jb, Jt, Js (14 doubles) and Tc, Tb, Tbt (3 uint64). */
-void orc_derived(const orc_sys* s, double* d14, uint64_t* t3)
+ * Jb, Jt, Js, ufd (15 doubles) and Tc, Tb, Tbt (3 uint64). */
+void orc_derived(const orc_sys* s, double* d15, uint64_t* t3)
 {
-    double d[14] = {s->lam, s->wpi, s->cs, s->sig, s->u, s->V, s->w, s->q, s->m,
-                    s->E, s->Pc, s->Jb, s->Jt, s->Js};
-    memcpy(d14, d, sizeof d);
+    double d[15] = {s->lam, s->wpi, s->cs, s->sig, s->u, s->V, s->w, s->q, s->m,
+                    s->E, s->Pc, s->Jb, s->Jt, s->Js, s->ufd};
+    memcpy(d15, d, sizeof d);
     t3[0] = s->Tc; t3[1] = s->Tb; t3[2] = s->Tbt;
 }
 
@@ -357,7 +418,9 @@ static int orc_inside_grain(const orc_sys* s, const double p[3])
  * r = R sqrt(u0), theta = 2 pi u1, z = H (u2 - 1/2); the first attempt
  * outside every grain is kept.  Velocity from block (i, 0, INIT_VEL, 0):
  * normals (g1,g2) from (u0,u1), g3 from (u2,u3); v = (sig g1, sig g2,
- * u + sig g3), taken as the half-step velocity v^{-1/2}.  Q_d = q0_d. */
+ * u + sig g3), taken as the half-step velocity v^{-1/2}.  Field-driven flow:
+ * v_z = sig g3 + ufd T instead, T = -ln u0 of block (i, 0, INIT_VEL, 1).
+ * Q_d = q0_d. */
 int orc_init(orc_sys* s)
 {
     int bad = 0;
@@ -384,7 +447,14 @@ int orc_init(orc_sys* s)
         s->x[3 * i + 0] = p[0]; s->x[3 * i + 1] = p[1]; s->x[3 * i + 2] = p[2];
         s->v[3 * i + 0] = s->sig * g1;
         s->v[3 * i + 1] = s->sig * g2;
-        s->v[3 * i + 2] = s->u + s->sig * g3;
+        if (s->flags & ORC_F_FIELD_DRIVEN) {
+            /* time since the last collision: block (i, 0, INIT_VEL, 1), u0 */
+            uint64_t w1[4];
+            orc_draw(s, (uint64_t)i, 0, ORC_P_INIT_VEL, 1, w1);
+            s->v[3 * i + 2] = s->sig * g3 - s->ufd * log(orc_uniform(w1[0]));
+        } else {
+            s->v[3 * i + 2] = s->u + s->sig * g3;
+        }
     }
     for (int d = 0; d < s->nd; ++d) s->Q[d] = s->dq0[d];
     s->step = 0;
@@ -526,7 +596,10 @@ static int orc_segment_hits(const double x[3], const double xh[3], const double 
  *   inverse of Eq. (B.12); v = -v_r r_hat (Eqs. B.10-B.11) + v_z z_hat with
  *   v_z ~ N(u, sig^2) from the second block's (u0,u1) (g1); unless the
  *   literal flag is set a tangential N(0, sig^2) part (g2) is added, which the
- *   product form of Eq. (B.1) implies.                                       */
+ *   product form of Eq. (B.1) implies.
+ * Field-driven flow: phi(v_z) is the field-driven distribution above; the
+ *   face fluxes and flux-weighted speeds use it, and a side ion takes
+ *   v_z = sig g1 + ufd T with T = -ln u2 of the second block.              */
 static void orc_reinject(const orc_sys* s, int64_t i, double x[3], double v[3])
 {
     uint64_t b0[4], b1[4];
@@ -543,8 +616,12 @@ static void orc_reinject(const orc_sys* s, int64_t i, double x[3], double v[3])
         x[2] = bottom ? -0.5 * s->H : 0.5 * s->H;
         v[0] = s->sig * g1;
         v[1] = s->sig * g2;
-        v[2] = bottom ? orc_flux_inverse(orc_uniform(b0[3]), s->u, s->sig)
-                      : -orc_flux_inverse(orc_uniform(b0[3]), -s->u, s->sig);
+        if (s->flags & ORC_F_FIELD_DRIVEN)
+            v[2] = bottom ? orc_fd_inverse(orc_uniform(b0[3]), s->ufd, s->sig, 0)
+                          : -orc_fd_inverse(orc_uniform(b0[3]), s->ufd, s->sig, 1);
+        else
+            v[2] = bottom ? orc_flux_inverse(orc_uniform(b0[3]), s->u, s->sig)
+                          : -orc_flux_inverse(orc_uniform(b0[3]), -s->u, s->sig);
     } else {
         double th = 2.0 * ORC_PI * orc_uniform(b0[1]);
         double c = cos(th), sn = sin(th);
@@ -555,7 +632,9 @@ static void orc_reinject(const orc_sys* s, int64_t i, double x[3], double v[3])
         double vt = (s->flags & ORC_F_LITERAL_SIDE) ? 0.0 : s->sig * g2;
         v[0] = -vr * c - vt * sn;
         v[1] = -vr * sn + vt * c;
-        v[2] = s->u + s->sig * g1;
+        v[2] = (s->flags & ORC_F_FIELD_DRIVEN)
+                   ? s->sig * g1 - s->ufd * log(orc_uniform(b1[2]))   /* phi(v_z), Eq. (B.1) */
+                   : s->u + s->sig * g1;
     }
 }
 

@@ -26,6 +26,7 @@ LIB = os.path.join(HERE, "libodust_oracle.so")
 EV_NONE = -1
 EV_EXITED = -2
 FLAG_CONFINEMENT = 4
+FLAG_FIELD_DRIVEN = 8
 # grid of the confinement potential (Appendix A): intervals along r and along z
 CONF_NX = 32
 CONF_NZ = 32
@@ -86,6 +87,11 @@ def lib():
         L.orc_ion_current_oml.argtypes = [C.c_double] * 6
         L.orc_ion_current_oml.restype = C.c_double
         L.orc_num_threads.restype = C.c_int
+        for name in ("orc_fd_density", "orc_fd_tail", "orc_fd_head"):
+            getattr(L, name).argtypes = [C.c_double, C.c_double, C.c_double]
+            getattr(L, name).restype = C.c_double
+        L.orc_fd_inverse.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int]
+        L.orc_fd_inverse.restype = C.c_double
         L.orc_confinement_grid.argtypes = [P, C.c_int, C.c_int, dp]
         L.orc_set_confinement.argtypes = [P, dp, C.c_double, C.c_double, C.c_int]
         L.orc_confinement_terms.argtypes = [i32p, i32p]
@@ -131,6 +137,26 @@ def ion_current_oml(Q: float, a: float, n: float, Ti: float, mi: float, u: float
     return lib().orc_ion_current_oml(Q, a, n, Ti, mi, u)
 
 
+def fd_density(v: float, ufd: float, sig: float) -> float:
+    """Stationary v_z density of the field-driven collisional flow."""
+    return lib().orc_fd_density(v, ufd, sig)
+
+
+def fd_tail(x: float, ufd: float, sig: float) -> float:
+    """int_x^inf v phi(v) dv of the field-driven distribution."""
+    return lib().orc_fd_tail(x, ufd, sig)
+
+
+def fd_head(w: float, ufd: float, sig: float) -> float:
+    """-int_-inf^-w v phi(v) dv of the field-driven distribution."""
+    return lib().orc_fd_head(w, ufd, sig)
+
+
+def fd_inverse(uu: float, ufd: float, sig: float, top: bool) -> float:
+    """Flux-weighted inward speed at the bottom (top=False) or top face."""
+    return lib().orc_fd_inverse(uu, ufd, sig, 1 if top else 0)
+
+
 def confinement_terms():
     """(powers of r, powers of z) of the fifteen terms of Eq. (A.3), in the
     order of their coefficients alpha_0 .. alpha_14."""
@@ -161,7 +187,7 @@ def num_threads() -> int:
 class Oracle:
     """One dust system on the CPU, FP64, SI units."""
 
-    DERIVED = ("lam", "wpi", "cs", "sig", "u", "V", "w", "q", "m", "E", "Pc", "Jb", "Jt", "Js")
+    DERIVED = ("lam", "wpi", "cs", "sig", "u", "V", "w", "q", "m", "E", "Pc", "Jb", "Jt", "Js", "ufd")
 
     def __init__(self, w, n_ions: Optional[int] = None, init: bool = True):
         L = lib()
@@ -176,7 +202,7 @@ class Oracle:
                                int(w.flags), _dp(dust), self.nd)
         if not self._h:
             raise ValueError("oracle: invalid parameters")
-        d = np.zeros(14)
+        d = np.zeros(15)
         t = np.zeros(3, dtype=np.uint64)
         L.orc_derived(self._h, _dp(d), t.ctypes.data_as(C.POINTER(C.c_uint64)))
         self.derived = dict(zip(self.DERIVED, d.tolist()))

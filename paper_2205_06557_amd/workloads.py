@@ -29,6 +29,7 @@ CHARGE_GIVEN, CHARGE_OML, CHARGE_CONSISTENT = 0, 1, 2
 FLAG_LITERAL_SIDE = 1            # side injection: radial + v_z only
 FLAG_NO_ION_ION = 2              # test-particle mode (ion-ion force off)
 FLAG_CONFINEMENT = 4             # confinement field of the outer plasma (Appendix A)
+FLAG_FIELD_DRIVEN = 8            # field-driven collisional flow: injection from its stationary distribution
 
 
 def ev_to_kelvin(t_ev: float) -> float:
