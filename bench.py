@@ -161,6 +161,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 256 MiB device copy first (reference for memory counters)")
+    ap.add_argument("--confinement", action="store_true",
+                    help="add the confinement field of the outer plasma (Appendix A)")
     ap.add_argument("--batch", action="store_true",
                     help="the batched 64-system sweep instead of the 2^20-ion two-grain workload")
     args = ap.parse_args()
@@ -190,8 +192,14 @@ def main():
               flush=True)
         del src, dst, flush
     w = W.two_grain_wake().with_(n_ions=args.n_ions)
+    if args.confinement:
+        w = w.with_(flags=int(w.flags) | W.FLAG_CONFINEMENT)
     prec = B.PREC_FP64 if args.fp64 else B.PREC_FP32
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter()
     sysm = B.System(w, precision=prec)
+    torch.cuda.synchronize()
+    setup_ms = 1e3 * (time.perf_counter() - t_setup)
     N = sysm.N
     print(f"[bench] {w.name}: N={N} grains={len(w.dust)} precision={'fp64' if prec else 'fp32'}",
           file=sys.stderr, flush=True)
@@ -233,8 +241,11 @@ def main():
         "dtype": "f64" if prec else "f32",
         "data": "synthetic",
         "config": {"workload": f"two-grain wake pair, N={N} ions, 2 grains (r=5um, z=-/+0.25 r_De), "
-                               "Mach 1, nu=0.1 omega_pi, R=3 r_De, H=8 r_De, dt=0.01/omega_pi",
-                   "n_ions": N, "n_dust": len(w.dust), "precision": "fp64" if prec else "fp32"},
+                               "Mach 1, nu=0.1 omega_pi, R=3 r_De, H=8 r_De, dt=0.01/omega_pi"
+                               + (", confinement field on" if args.confinement else ""),
+                   "n_ions": N, "n_dust": len(w.dust), "precision": "fp64" if prec else "fp32",
+                   "confinement": bool(args.confinement)},
+        "setup_ms": setup_ms,
         "pair_interactions_per_s": pairs,
         "roofline": {
             "bound": "alu",

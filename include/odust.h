@@ -61,6 +61,12 @@ typedef enum {
                                     (Appendix A): computed once, from the ions placed by
                                     initialisation, and added to every ion's acceleration
                                     and, as Q_d E_out, to the force of Eq. (1) */
+#define OD_FLAG_FIELD_DRIVEN 8u  /* field-driven collisional flow: initial and injected v_z
+                                    follow the flow's stationary distribution, a Gaussian of
+                                    width sigma convolved with an exponential of mean a/nu
+                                    (a = eE/m_i), the phi(v_z) of Eq. (B.1) for this flow;
+                                    without it v_z is N(M c_s, sigma^2).  Needs nu_in > 0 and
+                                    a/nu > sigma/30, else OD_EINVAL */
 
 /* od_sim.precision */
 #define OD_PREC_FP32 0           /* FP32 state and pair tiles, FP64 charge/force sums */

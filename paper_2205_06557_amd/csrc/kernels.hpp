@@ -74,11 +74,15 @@ struct PairArgs {
     ConfField cf;   // confinement field, added to every ion when cf.on
 };
 
+constexpr unsigned kFlagLiteralSide = 1u;   // side injection without the tangential part
+constexpr unsigned kFlagFieldDriven = 8u;   // field-driven collisional flow distribution
+
 struct PushArgs {
     int N, Npad, nd;
     unsigned flags;
     double dt, sig, ubar, R, H;
     uint64_t k0, k1, Tc, Tb, Tbt;
+    double ufd;     // field-driven flow: mean drift gained between collisions, a / nu
 };
 
 struct FinalArgs {
@@ -354,6 +358,58 @@ __device__ double flux_speed(double uu, double m, double s)
     return v;
 }
 
+// Field-driven collisional flow (constant-frequency charge exchange in a
+// homogeneous field): in the stationary flow v_z = sig g + ufd T with g
+// standard normal and T ~ Exp(1) the time since the last collision in units
+// of 1/nu.  With A(x) = exp(c - x/ufd) Phi(x/sig - sig/ufd), c = sig^2 /
+// (2 ufd^2), its density is A(x)/ufd and, integrating by parts,
+//   int_x^inf v phi dv      = (x + ufd) A(x) + sig pdf(x/sig) + ufd Phic(x/sig),
+//   -int_-inf^-w v phi dv   = (ufd - w) A(-w) + sig pdf(w/sig) - ufd Phic(w/sig).
+// A is evaluated through erfcx where its argument is non-negative, so that
+// neither factor overflows.
+__device__ inline double fd_A(double x, double ufd, double sig)
+{
+    const double z = (sig / ufd - x / sig) * 0.70710678118654752440;
+    if (z >= 0.0) return 0.5 * exp(-0.5 * (x / sig) * (x / sig)) * erfcx(z);
+    const double r = sig / ufd;
+    return 0.5 * exp(0.5 * r * r - x / ufd) * erfc(z);
+}
+
+// Flux-weighted inward speed at the bottom (top = false, v_z = s) or top
+// (v_z = -s) face for the field-driven distribution: the s >= 0 whose flux
+// tail is uu times the face's inflow.  Safeguarded Newton as flux_speed.
+__device__ double fd_speed(double uu, double ufd, double sig, bool top)
+{
+    const double k = 0.70710678118654752440;
+    auto tail = [&](double v, double& slope) {
+        if (top) {
+            const double A = fd_A(-v, ufd, sig);
+            slope = -v * A / ufd;
+            return (ufd - v) * A + sig * npdf(v / sig) - ufd * 0.5 * erfc(v / sig * k);
+        }
+        const double A = fd_A(v, ufd, sig);
+        slope = -v * A / ufd;
+        return (v + ufd) * A + sig * npdf(v / sig) + ufd * 0.5 * erfc(v / sig * k);
+    };
+    double slope;
+    const double goal = uu * tail(0.0, slope);
+    double lo = 0.0, hi = 40.0 * sig + (top ? 0.0 : 50.0 * ufd);
+    double v = top ? sig : ufd + sig;
+    for (int it = 0; it < 400; ++it) {
+        const double g = tail(v, slope) - goal;
+        if (g > 0.0) lo = v; else hi = v;
+        double nv = 0.5 * (lo + hi);
+        if (slope < 0.0) {
+            const double cand = v - g / slope;
+            if (cand >= lo && cand <= hi) nv = cand;
+        }
+        const bool done = fabs(nv - v) <= 1e-13 * sig;
+        v = nv;
+        if (done) break;
+    }
+    return v;
+}
+
 // New position and velocity of a lost ion, from blocks (i, n, REINJ, 0/1).
 __device__ void reinject(const PushArgs& p, uint64_t ion, uint64_t n, double o[6])
 {
@@ -371,8 +427,12 @@ __device__ void reinject(const PushArgs& p, uint64_t ion, uint64_t n, double o[6
         o[2] = bottom ? -0.5 * p.H : 0.5 * p.H;
         o[3] = p.sig * g1;
         o[4] = p.sig * g2;
-        o[5] = bottom ? flux_speed(unit(a.w[3]), p.ubar, p.sig)
-                      : -flux_speed(unit(a.w[3]), -p.ubar, p.sig);
+        if (p.flags & kFlagFieldDriven)
+            o[5] = bottom ? fd_speed(unit(a.w[3]), p.ufd, p.sig, false)
+                          : -fd_speed(unit(a.w[3]), p.ufd, p.sig, true);
+        else
+            o[5] = bottom ? flux_speed(unit(a.w[3]), p.ubar, p.sig)
+                          : -flux_speed(unit(a.w[3]), -p.ubar, p.sig);
     } else {                                    // side wall
         double sn, cs;
         sincos(2.0 * kPi * unit(a.w[1]), &sn, &cs);
@@ -380,10 +440,12 @@ __device__ void reinject(const PushArgs& p, uint64_t ion, uint64_t n, double o[6
         o[1] = p.R * sn;
         o[2] = p.H * (unit(a.w[2]) - 0.5);
         const double vr = p.sig * sqrt(-2.0 * log(unit(a.w[3])));
-        const double vt = (p.flags & 1u) ? 0.0 : p.sig * g2;
+        const double vt = (p.flags & kFlagLiteralSide) ? 0.0 : p.sig * g2;
         o[3] = -vr * cs - vt * sn;
         o[4] = -vr * sn + vt * cs;
-        o[5] = p.ubar + p.sig * g1;
+        // v_z from phi(v_z); the field-driven flow adds T = -ln u2 of block 1
+        o[5] = (p.flags & kFlagFieldDriven) ? p.sig * g1 - p.ufd * log(unit(b.w[2]))
+                                            : p.ubar + p.sig * g1;
     }
 }
 
@@ -697,8 +759,14 @@ __device__ __forceinline__ void init_ion(T* __restrict__ X, T* __restrict__ Y, T
     double g1, g2, g3, g4;
     gauss2(unit(g.w[0]), unit(g.w[1]), g1, g2);
     gauss2(unit(g.w[2]), unit(g.w[3]), g3, g4);
+    double vz = p.ubar + p.sig * g3;
+    if (p.flags & kFlagFieldDriven) {
+        // time since the last collision from block (i, 0, INIT_VEL, 1)
+        const U64x4 t = philox((uint64_t)i, 0, kInitVel, 1, p.k0, p.k1);
+        vz = p.sig * g3 - p.ufd * log(unit(t.w[0]));
+    }
     X[i] = (T)px; Y[i] = (T)py; Z[i] = (T)pz;
-    VX[i] = (T)(p.sig * g1); VY[i] = (T)(p.sig * g2); VZ[i] = (T)(p.ubar + p.sig * g3);
+    VX[i] = (T)(p.sig * g1); VY[i] = (T)(p.sig * g2); VZ[i] = (T)vz;
 }
 
 template <typename T>

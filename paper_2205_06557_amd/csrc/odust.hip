@@ -151,8 +151,17 @@ od_status check_params(const od_plasma* pl, const od_sim* sim, const od_dust* du
     if (sim->charge_mode < 0 || sim->charge_mode > 2) return fail(OD_EINVAL, "bad charge_mode");
     if (sim->precision != OD_PREC_FP32 && sim->precision != OD_PREC_FP64)
         return fail(OD_EINVAL, "bad precision");
-    if (sim->flags & ~(OD_FLAG_LITERAL_SIDE | OD_FLAG_NO_ION_ION | OD_FLAG_CONFINEMENT))
+    if (sim->flags & ~(OD_FLAG_LITERAL_SIDE | OD_FLAG_NO_ION_ION | OD_FLAG_CONFINEMENT | OD_FLAG_FIELD_DRIVEN))
         return fail(OD_EINVAL, "unknown flags");
+    if (sim->flags & OD_FLAG_FIELD_DRIVEN) {
+        // drift gained between collisions a / nu against the thermal speed
+        const double cs = std::sqrt(kKB * pl->T_e / pl->m_i);
+        const double E = std::isnan(pl->E_ext) ? pl->m_i * pl->nu_in * pl->mach * cs / kQE : pl->E_ext;
+        const double ufd = pl->nu_in > 0 ? kQE * E / (pl->m_i * pl->nu_in) : 0.0;
+        const double sig = std::sqrt(kKB * pl->T_i / pl->m_i);
+        if (!(pl->nu_in > 0) || !(ufd > 0) || sig > 30.0 * ufd)
+            return fail(OD_EINVAL, "field-driven flow needs nu_in > 0 and a drift a/nu above sigma/30");
+    }
     if (sim->reserved != 0) return fail(OD_EINVAL, "reserved must be 0");
     for (int d = 0; d < nd; ++d) {
         const od_dust& g = dust[d];
@@ -219,8 +228,17 @@ void derive_consts(const od_plasma& P, const od_sim& S, const od_dust* dust, int
 
     // face inflows per unit density (Appendix B), dimensionless
     auto face = [&](double m) { return m * normal_cdf(m / sig) + sig * normal_pdf(m / sig); };
-    const double Jb = kPI * R * R * face(ubar);
-    const double Jt = kPI * R * R * face(-ubar);
+    double Jb = kPI * R * R * face(ubar);
+    double Jt = kPI * R * R * face(-ubar);
+    const double ufd = nu > 0 ? Ez / nu : 0.0;
+    if (S.flags & OD_FLAG_FIELD_DRIVEN) {
+        // inflows of the field-driven distribution: A(0) = e^c Phi(-sig/ufd)
+        const double r = sig / ufd;
+        const double A0 = std::exp(0.5 * r * r) * normal_cdf(-r);
+        const double tail0 = ufd * A0 + sig * normal_pdf(0.0) + 0.5 * ufd;
+        Jb = kPI * R * R * tail0;
+        Jt = kPI * R * R * (tail0 - ufd);
+    }
     const double Js = 2.0 * kPI * R * H * sig / std::sqrt(2.0 * kPI);
     const double J = Jb + Jt + Js;
 
@@ -239,6 +257,7 @@ void derive_consts(const od_plasma& P, const od_sim& S, const od_dust* dust, int
     pu.Tc = prob_to_threshold(Pc);
     pu.Tb = prob_to_threshold(Jb / J);
     pu.Tbt = prob_to_threshold((Jb + Jt) / J);
+    pu.ufd = ufd;
 
     odk::FinalArgs& fa = c.fa;
     fa.nd = nd;

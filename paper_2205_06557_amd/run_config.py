@@ -87,11 +87,19 @@ def main(argv=None):
     ap.add_argument("--discard", type=int, default=None)
     ap.add_argument("--n-ions", type=int, default=None)
     ap.add_argument("--fp64", action="store_true")
+    ap.add_argument("--field-driven", action="store_true",
+                    help="inject from the field-driven flow's stationary distribution")
+    ap.add_argument("--confinement", action="store_true",
+                    help="add the confinement field of the outer plasma")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     w = NAMES[a.name](a)
     if a.n_ions:
         w = w.with_(n_ions=a.n_ions)
+    flags = int(w.flags) | (W.FLAG_FIELD_DRIVEN if a.field_driven else 0) | \
+        (W.FLAG_CONFINEMENT if a.confinement else 0)
+    w = w.with_(flags=flags, name=w.name + (" field-driven" if a.field_driven else "") +
+                (" confinement" if a.confinement else ""))
     steps = a.steps or w.n_steps
     disc = a.discard if a.discard is not None else min(w.n_discard, steps // 2)
     print(f"[run] {w.name}: N={w.n_ions}, {steps} steps, averages after {disc}", flush=True)
