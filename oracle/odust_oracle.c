@@ -90,6 +90,10 @@ typedef struct orc_sys {
      * P(r, z) = sum_m alpha_m (r/rs)^(2 a_m) (z/zs)^(2 b_m), in volts */
     int conf_on;
     double conf_alpha[15], conf_rs, conf_zs;
+    /* ion-ion cutoff with a switching function (Section 4, performance with
+     * cutoff): r_sw < r_cut in m, cut_on = 0 for the plain all-pairs sum */
+    int cut_on;
+    double r_sw, r_cut;
 } orc_sys;
 
 /* Exponent pairs (a, b) of the fifteen terms r^(2a) z^(2b) of Eq. (A.3), in
@@ -484,7 +488,22 @@ static void orc_accel_one(const orc_sys* s, int64_t i, double out[3])
             double dy = xi[1] - s->x[3 * j + 1];
             double dz = xi[2] - s->x[3 * j + 2];
             double r = sqrt(dx * dx + dy * dy + dz * dz);
-            double f = k * s->q * (1.0 + r / s->lam) * exp(-r / s->lam) / (r * r * r);
+            double f;
+            if (s->cut_on) {
+                if (r >= s->r_cut) continue;
+                /* switched energy phi(r) S(r): field -d(phi S)/dr along the unit vector */
+                double phi = k * s->q * exp(-r / s->lam) / r;
+                double dphi = -phi * (1.0 / r + 1.0 / s->lam);
+                double S = 1.0, dS = 0.0;
+                if (r > s->r_sw) {
+                    double wd = s->r_cut - s->r_sw, x = (r - s->r_sw) / wd;
+                    S = 1.0 - 6.0 * pow(x, 5) + 15.0 * pow(x, 4) - 10.0 * pow(x, 3);
+                    dS = (-30.0 * pow(x, 4) + 60.0 * pow(x, 3) - 30.0 * pow(x, 2)) / wd;
+                }
+                f = -(dphi * S + phi * dS) / r;
+            } else {
+                f = k * s->q * (1.0 + r / s->lam) * exp(-r / s->lam) / (r * r * r);
+            }
             ex += f * dx; ey += f * dy; ez += f * dz;
         }
     }
@@ -891,6 +910,22 @@ void orc_set_confinement(orc_sys* s, const double* alpha, double rs, double zs, 
     s->conf_rs = rs;
     s->conf_zs = zs;
     s->conf_on = on ? 1 : 0;
+}
+
+/* Ion-ion cutoff (Section 4: a switching function that vanishes beyond a
+ * fixed cutoff distance).  Reading: the screened Coulomb energy of a pair,
+ * phi(r) = q^2 exp(-r/r_De) / (4 pi eps0 r), is multiplied by the smooth
+ * step S(r) = 1 for r <= r_sw, 1 - 6x^5 + 15x^4 - 10x^3 with
+ * x = (r - r_sw)/(r_cut - r_sw) between, 0 from r_cut on (the switching
+ * function of the molecular-dynamics engine the paper runs on), and the
+ * force is minus the gradient of phi S.  Only the ion-ion interaction is
+ * switched; grain terms and the sum of Eq. (1) stay complete.  r_cut <= 0
+ * restores the plain sum. */
+void orc_set_cutoff(orc_sys* s, double r_sw, double r_cut)
+{
+    s->cut_on = r_cut > 0.0;
+    s->r_sw = r_sw;
+    s->r_cut = r_cut;
 }
 
 /* Exponents (powers of r and of z, as printed in Eq. (A.3)) of the terms. */

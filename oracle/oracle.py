@@ -92,6 +92,7 @@ def lib():
             getattr(L, name).restype = C.c_double
         L.orc_fd_inverse.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int]
         L.orc_fd_inverse.restype = C.c_double
+        L.orc_set_cutoff.argtypes = [P, C.c_double, C.c_double]
         L.orc_confinement_grid.argtypes = [P, C.c_int, C.c_int, dp]
         L.orc_set_confinement.argtypes = [P, dp, C.c_double, C.c_double, C.c_int]
         L.orc_confinement_terms.argtypes = [i32p, i32p]
@@ -274,6 +275,12 @@ class Oracle:
         a = np.zeros((len(idx), 3))
         lib().orc_accel_subset(self._h, idx.ctypes.data_as(C.POINTER(C.c_int64)), len(idx), _dp(a))
         return a
+
+    # --- ion-ion cutoff with a switching function ----------------------
+    def set_cutoff(self, r_switch: float, r_cut: float):
+        """Switch the ion-ion energy off between r_switch and r_cut (m);
+        r_cut <= 0 restores the plain all-pairs sum."""
+        lib().orc_set_cutoff(self._h, float(r_switch), float(r_cut))
 
     # --- confinement field (Appendix A) ---------------------------------
     def confinement_grid(self, nx: int = CONF_NX, nz: int = CONF_NZ) -> np.ndarray:
