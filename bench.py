@@ -81,6 +81,71 @@ def cpu_baseline(w, sysm, target_s: float):
     }
 
 
+FLOP_PER_CUT_PAIR = 40       # algorithmic FP32 flop per evaluated pair of the switched force
+
+
+def cutoff_bench(args):
+    """Constant-concentration series with the ion-ion cutoff (r_cut = 4,
+    switched from 3 Debye lengths): the domain grows with N (2^16 ions per
+    6 r_De of height), one grain at the origin.  Times K steps at each N,
+    fits t ~ N^beta, and reports the largest N's rate as the value."""
+    import numpy as np
+    import torch
+    from paper_2205_06557_amd import binding as B
+    from paper_2205_06557_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    series = []
+    for lg in range(17, 23):
+        w = W.long_domain(1 << lg)
+        s = B.System(w)
+        s.set_cutoff(W.CUTOFF_SWITCH, W.CUTOFF_RADIUS)
+        s.step(args.warmup)
+        s.sync()
+        s.set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(args.steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kt = s.kernel_times()
+        s.set_timing(False)
+        ns, npairs = s.cutoff_info()
+        s.close()
+        pair_ms = kt["pair"][0] / max(kt["pair"][1], 1)
+        row = {"n_ions": w.n_ions, "H_over_lambda": w.H / w.lam, "slabs": ns,
+               "ms_per_step": 1e3 * wall / args.steps, "pair_ms": pair_ms,
+               "pairs_evaluated": npairs, "sources_per_ion": npairs / w.n_ions,
+               "ion_steps_per_s": w.n_ions * args.steps / wall}
+        series.append(row)
+        print(f"[bench] cutoff N=2^{lg}: {row['ms_per_step']:.2f} ms/step, "
+              f"{row['sources_per_ion']:.0f} sources per ion", file=sys.stderr, flush=True)
+    n = np.array([r["n_ions"] for r in series], dtype=float)
+    t = np.array([r["ms_per_step"] for r in series])
+    beta = float(np.polyfit(np.log(n), np.log(t), 1)[0])
+    last = series[-1]
+    achieved = FLOP_PER_CUT_PAIR * last["pairs_evaluated"] / (last["pair_ms"] * 1e-3)
+    res = {
+        "metric": "ion-steps/s with the ion-ion cutoff, constant-concentration series",
+        "value": last["ion_steps_per_s"],
+        "unit": "ion-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": last["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "one 5 um grain, R = 3 r_De, H = 6 r_De N/2^16, Mach 1, "
+                               "nu = 0.1 omega_pi, cutoff 4 r_De switched from 3 r_De",
+                   "n_ions": last["n_ions"]},
+        "time_exponent_beta": beta,
+        "series": series,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
+                     "kernel": "slab sort + pair_cut (evaluated pairs)",
+                     "flop_per_pair": FLOP_PER_CUT_PAIR, "launch_ms": last["pair_ms"]},
+    }
+    print(json.dumps(res), flush=True)
+
+
 def batch_bench(args):
     """Batched sweep: 64 single-grain systems, log2 N ~ U(14, 17), Mach, radius
     and collision frequency drawn per system; one launch per phase for all
@@ -163,12 +228,17 @@ def main():
                     help="run a plain 256 MiB device copy first (reference for memory counters)")
     ap.add_argument("--confinement", action="store_true",
                     help="add the confinement field of the outer plasma (Appendix A)")
+    ap.add_argument("--cutoff", action="store_true",
+                    help="the constant-concentration series with the ion-ion cutoff")
     ap.add_argument("--batch", action="store_true",
                     help="the batched 64-system sweep instead of the 2^20-ion two-grain workload")
     args = ap.parse_args()
     if args.batch and args.gpus == 1:
         sys.path.insert(0, ROOT)
         batch_bench(args)
+        return
+    if args.cutoff and args.gpus == 1:
+        cutoff_bench(args)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path here "

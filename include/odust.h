@@ -165,6 +165,27 @@ const char* od_last_error(void);
  * acceleration r_De omega_pi^2 (m/s^2)}. */
 od_status od_get_units(od_system* sys, double* units_host);
 
+/* Ion-ion cutoff with a switching function (Section 4: the option for long
+ * domains, a switching function that is zero beyond a fixed cutoff
+ * distance).  The screened Coulomb energy of an ion pair is multiplied by
+ * S(r) = 1 for r <= r_switch, 1 - 6x^5 + 15x^4 - 10x^3 with
+ * x = (r - r_switch)/(r_cut - r_switch) up to r_cut, and 0 beyond; the ion
+ * force is minus the gradient of that energy.  Grain terms and the sum of
+ * Eq. (1) stay complete.  Distances in m; r_cut <= 0 returns to the
+ * all-pairs sum.  FP32 systems only (OD_EINVAL otherwise); needs
+ * 0 <= r_switch < r_cut.  Each step then sorts the ions into slabs along z
+ * (width >= r_cut, at most 1024 slabs) and evaluates, for every block of 256
+ * sorted ions, only the sources of its slabs and their two neighbours.
+ * Allocates the sort buffers (about 20 bytes per ion plus 4 bytes per slab
+ * and block of 256 ions) with the system's allocator; synchronises the
+ * system's stream. */
+od_status od_set_cutoff(od_system* sys, double r_switch, double r_cut);
+
+/* Cutoff bookkeeping of the last step: *nslab slabs and *pairs_evaluated,
+ * the ion pairs the cutoff kernel evaluated (targets x staged sources,
+ * padding included).  OD_ESTATE without a cutoff.  Synchronises. */
+od_status od_get_cutoff_info(od_system* sys, int32_t* nslab, int64_t* pairs_evaluated);
+
 /* Confinement field of a system created with OD_FLAG_CONFINEMENT (Appendix A).
  * At creation the potential of Eq. (A.1) -- the screened potential
  * k_B T_e / e of an infinite homogeneous ion background minus the screened

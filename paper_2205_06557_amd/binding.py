@@ -96,11 +96,13 @@ def lib():
         L.od_get_kernel_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.od_get_confinement.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                          C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.od_set_cutoff.argtypes = [vp, C.c_double, C.c_double]
+        L.od_get_cutoff_info.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
         for name in ("od_init_system", "od_step", "od_sync", "od_get_dust_charges",
                      "od_get_dust_forces", "od_get_units", "od_get_sizes", "od_get_state",
                      "od_set_state", "od_get_accelerations", "od_get_step_events",
                      "od_rng_block", "od_set_timing", "od_get_kernel_times",
-                     "od_get_confinement"):
+                     "od_get_confinement", "od_set_cutoff", "od_get_cutoff_info"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -250,6 +252,16 @@ class System:
         """(coefficients [15] in volts, grid [nr+1, nz+1] in volts) of the
         confinement field fitted at creation."""
         return _confinement(lambda *a: lib().od_get_confinement(self._h, *a))
+
+    def set_cutoff(self, r_switch: float, r_cut: float):
+        """Ion-ion cutoff with a switching function (distances in m); r_cut <= 0 removes it."""
+        _check(lib().od_set_cutoff(self._h, float(r_switch), float(r_cut)))
+
+    def cutoff_info(self):
+        """(number of slabs, ion pairs evaluated in the last step)."""
+        ns, npairs = C.c_int32(0), C.c_int64(0)
+        _check(lib().od_get_cutoff_info(self._h, C.byref(ns), C.byref(npairs)))
+        return ns.value, npairs.value
 
     def events(self):
         ev = np.zeros(self.N, dtype=np.uint8)

@@ -102,6 +102,62 @@ struct FinalArgs {
 };
 
 // ---------------------------------------------------------------------------
+// End of a block of 256 target ions: adds (when epi) the grain terms in FP64
+// (N_d per ion), the drive and the confinement field to the ion-ion sum
+// (gx, gy, gz), writes the acceleration to slot `out` of the output planes,
+// and adds the block's share of the Eq. (1) sums to the int64 fixed-point
+// accumulators.
+template <int BLOCK>
+__device__ __forceinline__ void pair_epilogue(float xi, float yi, float zi, int out, bool live,
+                                              double gx, double gy, double gz, bool epi,
+                                              const PairArgs& p, const DustSet& ds,
+                                              Ctl* __restrict__ ctl, float* __restrict__ oX,
+                                              float* __restrict__ oY, float* __restrict__ oZ,
+                                              double (*red)[kMaxDust][3])
+{
+    if (epi) {
+        const double xd = xi, yd = yi, zd = zi;
+        gz += p.Ez;
+        if (p.cf.on) {
+            double ex, ey, ez;
+            conf_field(p.cf, xd, yd, zd, ex, ey, ez);
+            gx += ex; gy += ey; gz += ez;
+        }
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        for (int d = 0; d < ds.nd; ++d) {
+            const double rx = xd - ds.pos[d][0], ry = yd - ds.pos[d][1], rz = zd - ds.pos[d][2];
+            const double r2 = rx * rx + ry * ry + rz * rz;
+            const double r = sqrt(r2);
+            const double ir3 = 1.0 / (r2 * r);
+            const double kq = p.Kq * ctl->Q[d] * ir3;               // bare Coulomb on the ion
+            gx += kq * rx; gy += kq * ry; gz += kq * rz;
+            // Eq. (1) summand: (1 + rho) e^-rho / rho^3 (r_d - x_i)
+            double f = live ? -(1.0 + r) * exp(-r) * ir3 : 0.0;
+            double fx = wave_sum(f * rx), fy = wave_sum(f * ry), fz = wave_sum(f * rz);
+            if (lane == 0) {
+                red[wv][d][0] = fx;
+                red[wv][d][1] = fy;
+                red[wv][d][2] = fz;
+            }
+        }
+    }
+    if (live) {
+        oX[out] = (float)gx;
+        oY[out] = (float)gy;
+        oZ[out] = (float)gz;
+    }
+    if (epi) {
+        __syncthreads();
+        for (int t = threadIdx.x; t < ds.nd * 3; t += BLOCK) {
+            const int d = t / 3, c = t % 3;
+            double s = 0.0;
+            for (int w = 0; w < BLOCK / 64; ++w) s += red[w][d][c];
+            atomicAdd(&ctl->acc[d][c], to_fixed(s, kForceScale, &ctl->status));
+        }
+    }
+    __syncthreads();
+}
+
 // Forces, FP32 tiles.  One block's share of the pair sum: target ions
 // [i0, i0 + BLOCK) of one system (planes X/Y/Z, local indices) against the
 // sources [jb, je), one target per lane.  The block stages TJ sources at a
@@ -171,58 +227,10 @@ __device__ __forceinline__ void pair_block_f32(const float* __restrict__ X,
         }
     }
 
-    const bool live = i < p.N;
-    double gx = p.Cd * sx, gy = p.Cd * sy, gz = p.Cd * sz;
-    if (epi) {
-        // grain terms in FP64 (N_d per ion) and the drive
-        const double xd = xi, yd = yi, zd = zi;
-        gz += p.Ez;
-        if (p.cf.on) {
-            double ex, ey, ez;
-            conf_field(p.cf, xd, yd, zd, ex, ey, ez);
-            gx += ex; gy += ey; gz += ez;
-        }
-        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-        for (int d = 0; d < ds.nd; ++d) {
-            const double rx = xd - ds.pos[d][0], ry = yd - ds.pos[d][1], rz = zd - ds.pos[d][2];
-            const double r2 = rx * rx + ry * ry + rz * rz;
-            const double r = sqrt(r2);
-            const double ir3 = 1.0 / (r2 * r);
-            const double kq = p.Kq * ctl->Q[d] * ir3;               // bare Coulomb on the ion
-            gx += kq * rx; gy += kq * ry; gz += kq * rz;
-            // Eq. (1) summand: (1 + rho) e^-rho / rho^3 (r_d - x_i)
-            double f = live ? -(1.0 + r) * exp(-r) * ir3 : 0.0;
-            double fx = wave_sum(f * rx), fy = wave_sum(f * ry), fz = wave_sum(f * rz);
-            if (lane == 0) {
-                red[wv][d][0] = fx;
-                red[wv][d][1] = fy;
-                red[wv][d][2] = fz;
-            }
-        }
-    }
-    if (live) {
-        oX[i] = (float)gx;
-        oY[i] = (float)gy;
-        oZ[i] = (float)gz;
-    }
-    if (epi) {
-        __syncthreads();
-        for (int t = threadIdx.x; t < ds.nd * 3; t += BLOCK) {
-            const int d = t / 3, c = t % 3;
-            double s = 0.0;
-            for (int w = 0; w < BLOCK / 64; ++w) s += red[w][d][c];
-            atomicAdd(&ctl->acc[d][c], to_fixed(s, kForceScale, &ctl->status));
-        }
-    }
-    __syncthreads();
+    pair_epilogue<BLOCK>(xi, yi, zi, i, i < p.N, p.Cd * sx, p.Cd * sy, p.Cd * sz, epi, p, ds, ctl,
+                         oX, oY, oZ, red);
 }
 
-// Pair forces of one system.  The source range is cut into `nsplit` parts
-// (blocks [k * Npad/BLOCK, (k + 1) * Npad/BLOCK) take part k) so that small
-// systems still fill the chip; part k writes its partial acceleration to
-// planes k of `acc` (3 Npad apart), which the push adds in order.
-// Eight waves per SIMD (at most 64 VGPRs) keep the transcendental and LDS
-// latencies of the inner loop hidden.
 template <int BLOCK, int TJ>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8, 8)))
 void pair_forces_f32(const float* __restrict__ xs,

@@ -24,6 +24,7 @@
 
 #include "../../include/odust.h"
 #include "kernels.hpp"
+#include "cutoff.hpp"
 
 namespace {
 
@@ -101,6 +102,16 @@ struct od_system {
     odk::PushArgs pu{};
     odk::FinalArgs fa{};
     std::vector<double> conf_grid;      // dimensionless confinement potentials
+    // ion-ion cutoff (FP32): slab sort buffers
+    bool cut = false;
+    odk::CutArgs ca{};
+    float* xs_sorted = nullptr;         // [3][Npad] positions in slab order
+    int* idx_sorted = nullptr;          // [Npad] ion of each sorted slot
+    int* slab = nullptr;                // [Npad] slab of each ion
+    int* table = nullptr;               // [nslab][nblk] per-block counts, then offsets
+    int* slab_total = nullptr;          // [nslab]
+    int* slab_start = nullptr;          // [nslab + 1]
+    int nsplit_saved = 1;
     // device memory
     void* x = nullptr;
     void* v = nullptr;
@@ -132,6 +143,19 @@ void dev_free(od_system* s, void* p)
         s->alloc.release(s->alloc.ctx, p);
     else
         (void)hipFree(p);
+}
+
+void free_cutoff(od_system* s)
+{
+    dev_free(s, s->xs_sorted);
+    dev_free(s, s->idx_sorted);
+    dev_free(s, s->slab);
+    dev_free(s, s->table);
+    dev_free(s, s->slab_total);
+    dev_free(s, s->slab_start);
+    s->xs_sorted = nullptr;
+    s->idx_sorted = s->slab = s->table = s->slab_total = s->slab_start = nullptr;
+    s->cut = false;
 }
 
 od_status check_params(const od_plasma* pl, const od_sim* sim, const od_dust* dust, int nd)
@@ -413,7 +437,19 @@ od_status launch_step(od_system* s)
             if (!e) return fail(OD_EDEVICE, "hipEventCreate failed");
             HIPCHK(hipEventRecord(e, s->stream));
         }
-        if (k == 0) {
+        if (k == 0 && s->cut) {
+            const float* x = (const float*)s->x;
+            const int64_t P = s->Npad;
+            const int nb = s->ca.nblk;
+            odk::slab_count_kernel<<<nb, 256, 0, s->stream>>>(x + 2 * P, (int)s->N, s->ca, s->slab, s->table);
+            odk::slab_scan_kernel<<<s->ca.nslab, 256, 0, s->stream>>>(s->table, nb, s->slab_total);
+            odk::slab_start_kernel<<<1, odk::kMaxSlabs, 0, s->stream>>>(s->slab_total, s->ca.nslab, s->slab_start);
+            odk::slab_scatter_kernel<<<nb, 256, 0, s->stream>>>(
+                x, x + P, x + 2 * P, (int)s->N, s->ca, s->slab, s->table, s->slab_start, s->xs_sorted,
+                s->xs_sorted + P, s->xs_sorted + 2 * P, s->idx_sorted);
+            odk::pair_cut_kernel<kPairBlock, kPairTile><<<nb, kPairBlock, 0, s->stream>>>(
+                s->xs_sorted, s->idx_sorted, s->slab_start, (float*)s->a, s->pa, s->ca, s->ds, s->ctl);
+        } else if (k == 0) {
             if (s->prec == OD_PREC_FP32)
                 odk::pair_forces_f32<kPairBlock, kPairTile><<<gp * s->nsplit, kPairBlock, 0, s->stream>>>(
                     (const float*)s->x, (float*)s->a, s->pa, s->ds, s->ctl, s->nsplit);
@@ -619,7 +655,8 @@ od_status od_get_dust_forces(od_system* s, int32_t which, double* f)
 void od_destroy(od_system* s)
 {
     if (!s) return;
-    if (s->stream || true) (void)hipStreamSynchronize(s->stream);
+    (void)hipStreamSynchronize(s->stream);
+    free_cutoff(s);
     dev_free(s, s->x);
     dev_free(s, s->v);
     dev_free(s, s->a);
@@ -628,6 +665,81 @@ void od_destroy(od_system* s)
     dev_free(s, s->ctl);
     for (hipEvent_t e : s->evpool) (void)hipEventDestroy(e);
     delete s;
+}
+
+od_status od_set_cutoff(od_system* s, double r_switch, double r_cut)
+{
+    if (!s) return fail(OD_EINVAL, "null system");
+    HIPCHK(hipStreamSynchronize(s->stream));
+    if (!(r_cut > 0.0)) {
+        if (s->cut) {
+            free_cutoff(s);
+            s->nsplit = s->nsplit_saved;
+        }
+        return OD_OK;
+    }
+    if (s->prec != OD_PREC_FP32) return fail(OD_EINVAL, "the cutoff path runs in FP32 only");
+    if (!(r_switch >= 0.0) || !(r_switch < r_cut)) return fail(OD_EINVAL, "need 0 <= r_switch < r_cut");
+    const double H = s->sim.H / s->lam, rc = r_cut / s->lam, rs = r_switch / s->lam;
+    const int nslab = (int)std::min<double>(odk::kMaxSlabs, std::max(1.0, std::floor(H / rc)));
+    const int nblk = (int)(s->Npad / 256);
+    if (s->cut) free_cutoff(s);
+    else s->nsplit_saved = s->nsplit;
+    const size_t P = (size_t)s->Npad;
+    s->xs_sorted = (float*)dev_alloc(s, 3 * P * sizeof(float));
+    s->idx_sorted = (int*)dev_alloc(s, P * sizeof(int));
+    s->slab = (int*)dev_alloc(s, P * sizeof(int));
+    s->table = (int*)dev_alloc(s, (size_t)nslab * nblk * sizeof(int));
+    s->slab_total = (int*)dev_alloc(s, (size_t)nslab * sizeof(int));
+    s->slab_start = (int*)dev_alloc(s, (size_t)(nslab + 1) * sizeof(int));
+    if (!s->xs_sorted || !s->idx_sorted || !s->slab || !s->table || !s->slab_total || !s->slab_start) {
+        free_cutoff(s);
+        s->nsplit = s->nsplit_saved;
+        return fail(OD_ENOMEM, "device allocation of the slab sort failed");
+    }
+    // padding slots of the sorted copy sit far away and are never overwritten
+    const size_t npad = P - (size_t)s->N;
+    if (npad) {
+        std::vector<float> far(npad, 1.0e18f);
+        std::vector<int> none(npad, -1);
+        for (int c = 0; c < 3; ++c)
+            HIPCHK(hipMemcpy(s->xs_sorted + c * P + s->N, far.data(), npad * sizeof(float), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(s->idx_sorted + s->N, none.data(), npad * sizeof(int), hipMemcpyHostToDevice));
+    }
+    s->ca.nslab = nslab;
+    s->ca.nblk = nblk;
+    s->ca.z0 = (float)(-0.5 * H);
+    s->ca.inv_w = (float)(nslab / H);
+    s->ca.rsw = (float)rs;
+    s->ca.inv_sw = (float)(1.0 / (rc - rs));
+    s->cut = true;
+    s->nsplit = 1;
+    return OD_OK;
+}
+
+od_status od_get_cutoff_info(od_system* s, int32_t* nslab, int64_t* pairs_evaluated)
+{
+    if (!s) return fail(OD_EINVAL, "null system");
+    if (!s->cut) return fail(OD_ESTATE, "no cutoff is set");
+    const int ns = s->ca.nslab;
+    std::vector<int> start(ns + 1);
+    HIPCHK(hipMemcpyAsync(start.data(), s->slab_start, (ns + 1) * sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    if (nslab) *nslab = ns;
+    if (pairs_evaluated) {
+        // slab of sorted slot p: the s with start[s] <= p < start[s + 1]
+        auto slab_at = [&](int64_t p) {
+            return (int)(std::upper_bound(start.begin(), start.end(), (int)p) - start.begin()) - 1;
+        };
+        int64_t total = 0;
+        for (int64_t i0 = 0; i0 < s->N; i0 += 256) {
+            const int lo = slab_at(i0), hi = slab_at(std::min<int64_t>(i0 + 256, s->N) - 1);
+            const int64_t jb = start[std::max(lo - 1, 0)], je = start[std::min(hi + 2, ns)];
+            total += 256 * ((je - jb + kPairTile - 1) / kPairTile) * kPairTile;
+        }
+        *pairs_evaluated = total;
+    }
+    return OD_OK;
 }
 
 od_status od_get_confinement(od_system* s, double* coef, double* grid, int32_t* nr, int32_t* nz)
@@ -750,6 +862,7 @@ od_status od_get_accelerations(od_system* s, void* a)
 od_status od_set_pair_split(od_system* s, int32_t nsplit)
 {
     if (!s) return fail(OD_EINVAL, "null system");
+    if (s->cut) return fail(OD_ESTATE, "the pair sum is not split while a cutoff is set");
     if (nsplit < 1 || nsplit > kMaxSplitSingle) return fail(OD_EINVAL, "nsplit must be in [1,%d]", kMaxSplitSingle);
     if (s->prec != OD_PREC_FP32 && nsplit != 1) return fail(OD_EINVAL, "the FP64 mode does not split");
     if (nsplit > s->Npad / kPairBlock) return fail(OD_EINVAL, "more splits than source tiles");

@@ -134,6 +134,22 @@ def chain8(n_ions: int = 1 << 21, seed: int = 4) -> Workload:
                                           name=f"chain-8 N={n_ions}")
 
 
+def long_domain(n_ions: int = 1 << 20, seed: int = 5) -> Workload:
+    """The constant-concentration series of the cutoff study: one 5 um grain
+    at the origin, R = 3 lambda, and a height that grows with N so that the
+    superparticle density stays that of 2^16 ions in 6 lambda
+    (H = 6 lambda N / 2^16); otherwise the single-grain plasma (Mach 1,
+    nu = 0.1 omega_pi).  Used with an ion-ion cutoff of 4 lambda switched
+    from 3 lambda (CUTOFF_SWITCH, CUTOFF_RADIUS)."""
+    return single_grain_small(seed).with_(n_ions=n_ions, H=6 * _LAM * n_ions / (1 << 16),
+                                          n_steps=1000, n_discard=500,
+                                          name=f"long domain N={n_ions}")
+
+
+CUTOFF_SWITCH = 3 * _LAM
+CUTOFF_RADIUS = 4 * _LAM
+
+
 def paper_table2(n_ions: int = 1 << 16) -> Workload:
     """The paper's first test case (Table 2): Te = 29011 K, Ti = 290.11 K,
     n = 1e14, argon, M = 1, R = 3, H = 6 (Debye lengths), dt = 3.5148e-10 s,
