@@ -221,11 +221,31 @@ od_status od_set_state(od_system* sys, const void* x_host, const void* v_host, c
  * (float or double as the state). */
 od_status od_get_accelerations(od_system* sys, void* a_host);
 
-/* Source splits of the pair sum (FP32 mode): the sources are cut into nsplit
- * (1..4) ranges evaluated by separate blocks whose partial accelerations the
- * push adds in order, so that small systems fill the GPU.  Chosen at
- * creation for about four blocks per compute unit; changing it changes
- * rounding only. */
+/* All-pairs ion-ion kernel (FP32 systems with the ion-ion force).
+ * OD_PAIR_ONE_SIDED evaluates every ordered pair (one target per lane, all
+ * sources); OD_PAIR_SYMMETRIC evaluates each unordered pair once and applies
+ * the reaction to the source (Newton's third law of the screened Coulomb
+ * force), accumulating both sides in int64 fixed point (resolution 2^-20 of
+ * the raw pair sums), so the result does not depend on scheduling and is
+ * bitwise reproducible; it rounds differently from the one-sided kernel.
+ * OD_PAIR_AUTO (the default) takes the symmetric kernel from 2^16 ions.
+ * The symmetric kernel needs 24 bytes per ion of accumulators.  FP64 systems
+ * and the test-particle mode always use the one-sided kernel; a cutoff
+ * (od_set_cutoff) takes precedence over either.  od_get_pair_kernel reports
+ * the kernel in use. */
+#define OD_PAIR_AUTO 0
+#define OD_PAIR_ONE_SIDED 1
+#define OD_PAIR_SYMMETRIC 2
+od_status od_set_pair_kernel(od_system* sys, int32_t kind);
+od_status od_get_pair_kernel(od_system* sys, int32_t* kind);
+
+/* Source splits of the one-sided pair sum (FP32 mode): the sources are cut
+ * into nsplit (1..4) ranges evaluated by separate blocks whose partial
+ * accelerations the push adds in order, so that small systems fill the GPU.
+ * Chosen at creation for about four blocks per compute unit; changing it
+ * changes rounding only.  With the symmetric kernel or a cutoff the sum is
+ * not split: od_get_pair_split reports 1 and od_set_pair_split accepts only 1
+ * (OD_ESTATE otherwise). */
 od_status od_set_pair_split(od_system* sys, int32_t nsplit);
 od_status od_get_pair_split(od_system* sys, int32_t* nsplit);
 

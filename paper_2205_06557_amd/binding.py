@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libodust.so")
 
 OD_OK, OD_EINVAL, OD_EDEVICE, OD_ENUMERIC, OD_ESTATE, OD_ENOMEM = 0, -1, -2, -3, -4, -5
 PREC_FP32, PREC_FP64 = 0, 1
+PAIR_AUTO, PAIR_ONE_SIDED, PAIR_SYMMETRIC = 0, 1, 2
 EV_NONE, EV_EXIT, EV_ABS_BASE, EV_COLL_BIT = 0, 1, 2, 0x80
 KERNEL_CLASSES = ("pair", "push", "reinject", "finalize")
 
@@ -97,12 +98,18 @@ def lib():
         L.od_get_confinement.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                          C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.od_set_cutoff.argtypes = [vp, C.c_double, C.c_double]
+        L.od_set_pair_split.argtypes = [vp, C.c_int32]
+        L.od_get_pair_split.argtypes = [vp, C.POINTER(C.c_int32)]
+        L.od_set_pair_kernel.argtypes = [vp, C.c_int32]
+        L.od_get_pair_kernel.argtypes = [vp, C.POINTER(C.c_int32)]
         L.od_get_cutoff_info.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
         for name in ("od_init_system", "od_step", "od_sync", "od_get_dust_charges",
                      "od_get_dust_forces", "od_get_units", "od_get_sizes", "od_get_state",
                      "od_set_state", "od_get_accelerations", "od_get_step_events",
                      "od_rng_block", "od_set_timing", "od_get_kernel_times",
-                     "od_get_confinement", "od_set_cutoff", "od_get_cutoff_info"):
+                     "od_get_confinement", "od_set_cutoff", "od_get_cutoff_info",
+                     "od_set_pair_split", "od_get_pair_split", "od_set_pair_kernel",
+                     "od_get_pair_kernel"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -252,6 +259,24 @@ class System:
         """(coefficients [15] in volts, grid [nr+1, nz+1] in volts) of the
         confinement field fitted at creation."""
         return _confinement(lambda *a: lib().od_get_confinement(self._h, *a))
+
+    def set_pair_split(self, nsplit: int):
+        """Source splits of the one-sided pair sum (1..4)."""
+        _check(lib().od_set_pair_split(self._h, int(nsplit)))
+
+    def pair_split(self) -> int:
+        n = C.c_int32(0)
+        _check(lib().od_get_pair_split(self._h, C.byref(n)))
+        return n.value
+
+    def set_pair_kernel(self, kind: int):
+        """PAIR_AUTO, PAIR_ONE_SIDED or PAIR_SYMMETRIC."""
+        _check(lib().od_set_pair_kernel(self._h, int(kind)))
+
+    def pair_kernel(self) -> int:
+        k = C.c_int32(0)
+        _check(lib().od_get_pair_kernel(self._h, C.byref(k)))
+        return k.value
 
     def set_cutoff(self, r_switch: float, r_cut: float):
         """Ion-ion cutoff with a switching function (distances in m); r_cut <= 0 removes it."""
@@ -597,27 +622,3 @@ class Mlp:
                                        C.byref(cfg), _ptr(hist)))
         return hist
 
-
-def _split_sigs():
-    L = lib()
-    if not getattr(L, "_split_ok", False):
-        L.od_set_pair_split.argtypes = [C.c_void_p, C.c_int32]
-        L.od_get_pair_split.argtypes = [C.c_void_p, C.POINTER(C.c_int32)]
-        L.od_set_pair_split.restype = C.c_int
-        L.od_get_pair_split.restype = C.c_int
-        L._split_ok = True
-    return L
-
-
-def _system_set_pair_split(self, nsplit: int):
-    _check(_split_sigs().od_set_pair_split(self._h, int(nsplit)))
-
-
-def _system_pair_split(self) -> int:
-    n = C.c_int32(0)
-    _check(_split_sigs().od_get_pair_split(self._h, C.byref(n)))
-    return n.value
-
-
-System.set_pair_split = _system_set_pair_split
-System.pair_split = _system_pair_split

@@ -25,6 +25,7 @@
 #include "../../include/odust.h"
 #include "kernels.hpp"
 #include "cutoff.hpp"
+#include "pairsym.hpp"
 
 namespace {
 
@@ -39,6 +40,8 @@ constexpr int kPairTile = 256;
 constexpr int kPad = 256;
 constexpr int kReinjGrid = 2 * odk::kSlots;   // a multiple of the lost-list segments
 constexpr int kMaxSplitSingle = 4;             // source splits of one system's pair sum
+constexpr int kSymMinTiles = 256;             // all-pairs sum with each pair once from 2^16 ions
+constexpr double kSymItemsTarget = 16384.0;    // work items of the symmetric sum
 constexpr int kConfNr = 32, kConfNz = 32;      // intervals of the confinement grid along r, z
 constexpr int kConfNodes = (kConfNr + 1) * (kConfNz + 1);
 
@@ -111,7 +114,12 @@ struct od_system {
     int* table = nullptr;               // [nslab][nblk] per-block counts, then offsets
     int* slab_total = nullptr;          // [nslab]
     int* slab_start = nullptr;          // [nslab + 1]
-    int nsplit_saved = 1;
+    // all-pairs sum with each pair evaluated once
+    int pair_kind = OD_PAIR_AUTO;
+    bool sym = false;
+    unsigned long long* acc_fix = nullptr;  // [3][Npad] int64 fixed-point pair sums
+    odk::SymItem* sym_items = nullptr;
+    int n_sym_items = 0;
     // device memory
     void* x = nullptr;
     void* v = nullptr;
@@ -156,6 +164,67 @@ void free_cutoff(od_system* s)
     s->xs_sorted = nullptr;
     s->idx_sorted = s->slab = s->table = s->slab_total = s->slab_start = nullptr;
     s->cut = false;
+}
+
+void free_sym(od_system* s)
+{
+    dev_free(s, s->acc_fix);
+    dev_free(s, s->sym_items);
+    s->acc_fix = nullptr;
+    s->sym_items = nullptr;
+    s->n_sym_items = 0;
+    s->sym = false;
+}
+
+// Work items of the symmetric sum: runs of at most C source tiles J >= I of
+// each target tile row I, C chosen for about kSymItemsTarget items; longest
+// first, so that the short ones fill the tail.
+std::vector<odk::SymItem> sym_items(int T)
+{
+    const double pairs = 0.5 * (double)T * (T + 1);
+    const int C = (int)std::max(1.0, std::ceil(pairs / kSymItemsTarget));
+    std::vector<odk::SymItem> v;
+    for (int I = 0; I < T; ++I)
+        for (int J0 = I; J0 < T; J0 += C) v.push_back({I, J0, std::min(J0 + C, T), 0});
+    std::stable_sort(v.begin(), v.end(), [](const odk::SymItem& a, const odk::SymItem& b) {
+        return a.J1 - a.J0 > b.J1 - b.J0;
+    });
+    return v;
+}
+
+od_status setup_sym(od_system* s)
+{
+    if (s->sym) return OD_OK;
+    const int T = (int)(s->Npad / kPairBlock);
+    std::vector<odk::SymItem> items = sym_items(T);
+    s->acc_fix = (unsigned long long*)dev_alloc(s, 3 * (size_t)s->Npad * sizeof(unsigned long long));
+    s->sym_items = (odk::SymItem*)dev_alloc(s, items.size() * sizeof(odk::SymItem));
+    if (!s->acc_fix || !s->sym_items) {
+        free_sym(s);
+        return fail(OD_ENOMEM, "device allocation of the symmetric pair sum failed");
+    }
+    HIPCHK(hipMemcpyAsync(s->sym_items, items.data(), items.size() * sizeof(odk::SymItem),
+                          hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemsetAsync(s->acc_fix, 0, 3 * (size_t)s->Npad * sizeof(unsigned long long), s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->n_sym_items = (int)items.size();
+    s->sym = true;
+    return OD_OK;
+}
+
+// Chooses the all-pairs kernel for the system's kind and size.
+od_status apply_pair_kind(od_system* s)
+{
+    const bool able = s->prec == OD_PREC_FP32 && s->pa.ion_ion;
+    const bool want = able && (s->pair_kind == OD_PAIR_SYMMETRIC ||
+                               (s->pair_kind == OD_PAIR_AUTO && s->Npad / kPairBlock >= kSymMinTiles));
+    if (want && !s->sym) {
+        od_status st = setup_sym(s);
+        if (st != OD_OK) return st;
+    } else if (!want && s->sym) {
+        free_sym(s);
+    }
+    return OD_OK;
 }
 
 od_status check_params(const od_plasma* pl, const od_sim* sim, const od_dust* dust, int nd)
@@ -415,6 +484,10 @@ void derive(od_system* s)
     s->fa = c.fa;
 }
 
+// Partial-acceleration planes the push adds: the chosen source split for the
+// one-sided all-pairs kernel, one plane for the symmetric and cutoff paths.
+int eff_split(const od_system* s) { return (s->cut || s->sym) ? 1 : s->nsplit; }
+
 hipEvent_t next_event(od_system* s)
 {
     if (s->evnext == s->evpool.size()) {
@@ -449,6 +522,11 @@ od_status launch_step(od_system* s)
                 s->xs_sorted + P, s->xs_sorted + 2 * P, s->idx_sorted);
             odk::pair_cut_kernel<kPairBlock, kPairTile><<<nb, kPairBlock, 0, s->stream>>>(
                 s->xs_sorted, s->idx_sorted, s->slab_start, (float*)s->a, s->pa, s->ca, s->ds, s->ctl);
+        } else if (k == 0 && s->sym) {
+            odk::pair_sym_kernel<kPairBlock><<<s->n_sym_items, kPairBlock, 0, s->stream>>>(
+                (const float*)s->x, (int)s->Npad, (int)s->N, s->sym_items, s->acc_fix, s->ctl);
+            odk::pair_sym_epilogue<<<(int)(s->Npad / 256), 256, 0, s->stream>>>(
+                (const float*)s->x, s->acc_fix, (float*)s->a, s->pa, s->ds, s->ctl);
         } else if (k == 0) {
             if (s->prec == OD_PREC_FP32)
                 odk::pair_forces_f32<kPairBlock, kPairTile><<<gp * s->nsplit, kPairBlock, 0, s->stream>>>(
@@ -460,7 +538,7 @@ od_status launch_step(od_system* s)
             if (s->prec == OD_PREC_FP32)
                 odk::push_kernel<float><<<gq, 256, 0, s->stream>>>(
                     (float*)s->x, (float*)s->v, (const float*)s->a, s->ev, s->lost, s->pu, s->ds,
-                    s->ctl, s->nsplit);
+                    s->ctl, eff_split(s));
             else
                 odk::push_kernel<double><<<gq, 256, 0, s->stream>>>(
                     (double*)s->x, (double*)s->v, (const double*)s->a, s->ev, s->lost, s->pu, s->ds,
@@ -597,6 +675,7 @@ od_status od_init_system(const od_plasma* plasma, const od_sim* sim, const od_du
         s->pa = c.pa;
         s->fa = c.fa;
     }
+    if (st == OD_OK) st = apply_pair_kind(s);
     if (st != OD_OK) {
         od_destroy(s);
         return st;
@@ -657,6 +736,7 @@ void od_destroy(od_system* s)
     if (!s) return;
     (void)hipStreamSynchronize(s->stream);
     free_cutoff(s);
+    free_sym(s);
     dev_free(s, s->x);
     dev_free(s, s->v);
     dev_free(s, s->a);
@@ -672,10 +752,7 @@ od_status od_set_cutoff(od_system* s, double r_switch, double r_cut)
     if (!s) return fail(OD_EINVAL, "null system");
     HIPCHK(hipStreamSynchronize(s->stream));
     if (!(r_cut > 0.0)) {
-        if (s->cut) {
-            free_cutoff(s);
-            s->nsplit = s->nsplit_saved;
-        }
+        if (s->cut) free_cutoff(s);
         return OD_OK;
     }
     if (s->prec != OD_PREC_FP32) return fail(OD_EINVAL, "the cutoff path runs in FP32 only");
@@ -684,7 +761,6 @@ od_status od_set_cutoff(od_system* s, double r_switch, double r_cut)
     const int nslab = (int)std::min<double>(odk::kMaxSlabs, std::max(1.0, std::floor(H / rc)));
     const int nblk = (int)(s->Npad / 256);
     if (s->cut) free_cutoff(s);
-    else s->nsplit_saved = s->nsplit;
     const size_t P = (size_t)s->Npad;
     s->xs_sorted = (float*)dev_alloc(s, 3 * P * sizeof(float));
     s->idx_sorted = (int*)dev_alloc(s, P * sizeof(int));
@@ -694,7 +770,6 @@ od_status od_set_cutoff(od_system* s, double r_switch, double r_cut)
     s->slab_start = (int*)dev_alloc(s, (size_t)(nslab + 1) * sizeof(int));
     if (!s->xs_sorted || !s->idx_sorted || !s->slab || !s->table || !s->slab_total || !s->slab_start) {
         free_cutoff(s);
-        s->nsplit = s->nsplit_saved;
         return fail(OD_ENOMEM, "device allocation of the slab sort failed");
     }
     // padding slots of the sorted copy sit far away and are never overwritten
@@ -713,7 +788,6 @@ od_status od_set_cutoff(od_system* s, double r_switch, double r_cut)
     s->ca.rsw = (float)rs;
     s->ca.inv_sw = (float)(1.0 / (rc - rs));
     s->cut = true;
-    s->nsplit = 1;
     return OD_OK;
 }
 
@@ -846,10 +920,10 @@ od_status od_get_accelerations(od_system* s, void* a)
     od_status st = copy_soa_out(s, s->a, a);
     if (st != OD_OK) return st;
     HIPCHK(hipStreamSynchronize(s->stream));
-    if (s->nsplit > 1) {   // add the partial planes in the push's order
+    if (eff_split(s) > 1) {   // add the partial planes in the push's order
         std::vector<float> part(3 * (size_t)s->N);
         float* out = (float*)a;
-        for (int k = 1; k < s->nsplit; ++k) {
+        for (int k = 1; k < eff_split(s); ++k) {
             st = copy_soa_out(s, (const char*)s->a + (size_t)k * 3 * s->Npad * s->esz, part.data());
             if (st != OD_OK) return st;
             HIPCHK(hipStreamSynchronize(s->stream));
@@ -859,10 +933,33 @@ od_status od_get_accelerations(od_system* s, void* a)
     return OD_OK;
 }
 
+od_status od_set_pair_kernel(od_system* s, int32_t kind)
+{
+    if (!s) return fail(OD_EINVAL, "null system");
+    if (kind != OD_PAIR_AUTO && kind != OD_PAIR_ONE_SIDED && kind != OD_PAIR_SYMMETRIC)
+        return fail(OD_EINVAL, "unknown pair kernel kind %d", kind);
+    if (kind == OD_PAIR_SYMMETRIC && (s->prec != OD_PREC_FP32 || !s->pa.ion_ion))
+        return fail(OD_EINVAL, "the symmetric sum needs FP32 and the ion-ion force");
+    HIPCHK(hipStreamSynchronize(s->stream));
+    const int old = s->pair_kind;
+    s->pair_kind = kind;
+    od_status st = apply_pair_kind(s);
+    if (st != OD_OK) s->pair_kind = old;
+    return st;
+}
+
+od_status od_get_pair_kernel(od_system* s, int32_t* kind)
+{
+    if (!s || !kind) return fail(OD_EINVAL, "null argument");
+    *kind = s->sym ? OD_PAIR_SYMMETRIC : OD_PAIR_ONE_SIDED;
+    return OD_OK;
+}
+
 od_status od_set_pair_split(od_system* s, int32_t nsplit)
 {
     if (!s) return fail(OD_EINVAL, "null system");
-    if (s->cut) return fail(OD_ESTATE, "the pair sum is not split while a cutoff is set");
+    if (s->cut && nsplit != 1) return fail(OD_ESTATE, "the pair sum is not split while a cutoff is set");
+    if (s->sym && nsplit != 1) return fail(OD_ESTATE, "the symmetric pair sum is not split");
     if (nsplit < 1 || nsplit > kMaxSplitSingle) return fail(OD_EINVAL, "nsplit must be in [1,%d]", kMaxSplitSingle);
     if (s->prec != OD_PREC_FP32 && nsplit != 1) return fail(OD_EINVAL, "the FP64 mode does not split");
     if (nsplit > s->Npad / kPairBlock) return fail(OD_EINVAL, "more splits than source tiles");
@@ -874,7 +971,7 @@ od_status od_set_pair_split(od_system* s, int32_t nsplit)
 od_status od_get_pair_split(od_system* s, int32_t* nsplit)
 {
     if (!s || !nsplit) return fail(OD_EINVAL, "null argument");
-    *nsplit = s->nsplit;
+    *nsplit = eff_split(s);
     return OD_OK;
 }
 

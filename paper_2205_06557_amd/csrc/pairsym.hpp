@@ -1,0 +1,157 @@
+// pairsym.hpp -- the all-pairs ion-ion sum with each pair evaluated once.
+//
+// The screened Coulomb force is antisymmetric, so the tile pair (I, J) of
+// 256-ion target and source tiles also gives the reaction on the sources.
+// Work items are runs of tiles J in [J0, J1) of one target tile row I
+// (J >= I), longest first.  Within an item:
+//   * the diagonal tile (J == I) is summed one-sided (each ordered pair);
+//   * an off-diagonal tile is cut into four sub-tiles of 64 sources; lane l of
+//     a wave pairs its target with source (l + k) mod 64 in step k, adds the
+//     term to its own sum and subtracts it from a source accumulator that
+//     moves one lane down each step (a wavefront rotate), so that after 64
+//     steps every lane holds the reaction on one source, summed over the
+//     wave's 64 targets in a fixed order; the four waves' sums are added in
+//     LDS in a fixed order;
+//   * reactions go to the sources' int64 fixed-point accumulators once per
+//     tile pair, and the targets' sum once per item.
+// Fixed-point integer addition is exact and commutative, so the totals do
+// not depend on the order in which items run: results are deterministic.
+// A per-ion epilogue kernel converts the totals, adds the grain, drive and
+// confinement terms and the Eq. (1) sums (pair_epilogue), and clears the
+// accumulators for the next step.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace odk {
+
+// Resolution of the accumulators of the raw sums (1 + r) e^-r / r^3 d:
+// 2^-20, range 2^43 (a single pair overflows only below 3e-7 r_De).
+constexpr double kSymScale = 1048576.0;
+
+struct SymItem {
+    int I, J0, J1, pad_;
+};
+
+// One pair term (1 + r) e^-r / r^3 for the difference d.
+__device__ __forceinline__ float sym_f(float dx, float dy, float dz)
+{
+    const float kNegLog2e = -1.4426950408889634f;
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    const float ri = __builtin_amdgcn_rsqf(r2);
+    const float r = r2 * ri;
+    const float e = __builtin_amdgcn_exp2f(r * kNegLog2e);
+    const float ri2 = ri * ri;
+    return fmaf(ri2, ri, ri2) * e;
+}
+
+__device__ __forceinline__ float rotate_down(float v)
+{
+    // lane l receives the value of lane l + 1 (mod 64): DPP wave_rol:1
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x134, 0xf,
+                                                              0xf, true));
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8, 8)))
+void pair_sym_kernel(const float* __restrict__ xs, int Npad, int N, const SymItem* __restrict__ items,
+                     unsigned long long* __restrict__ acc_fix, Ctl* __restrict__ ctl)
+{
+    static_assert(BLOCK == 256, "four waves of 64");
+    __shared__ float4 src[4][128];          // sub-tiles of 64 sources, each stored twice
+    __shared__ float jpart[4][3][BLOCK];    // reactions per wave
+    const float* X = xs;
+    const float* Y = xs + Npad;
+    const float* Z = xs + 2 * Npad;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const SymItem it = items[blockIdx.x];
+    const int i = it.I * BLOCK + threadIdx.x;
+    const float xi = X[i], yi = Y[i], zi = Z[i];
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    for (int J = it.J0; J < it.J1; ++J) {
+        const int j0 = J * BLOCK;
+        __syncthreads();
+        {
+            const int st = threadIdx.x >> 6, l = threadIdx.x & 63;
+            const float4 q = make_float4(X[j0 + threadIdx.x], Y[j0 + threadIdx.x], Z[j0 + threadIdx.x], 0.0f);
+            src[st][l] = q;
+            src[st][l + 64] = q;
+        }
+        __syncthreads();
+        float ax = 0.0f, ay = 0.0f, az = 0.0f;
+        if (J == it.I) {
+            for (int k = 0; k < BLOCK; ++k) {
+                const float4 q = src[k >> 6][k & 63];
+                const float dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
+                float f = sym_f(dx, dy, dz);
+                f = (k == (int)threadIdx.x) ? 0.0f : f;
+                ax = fmaf(f, dx, ax);
+                ay = fmaf(f, dy, ay);
+                az = fmaf(f, dz, az);
+            }
+        } else {
+            for (int st = 0; st < 4; ++st) {
+                float jx = 0.0f, jy = 0.0f, jz = 0.0f;
+                const float4* base = &src[st][lane];
+#pragma unroll 16
+                for (int k = 0; k < 64; ++k) {
+                    const float4 q = base[k];                 // source (lane + k) mod 64
+                    const float dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
+                    const float f = sym_f(dx, dy, dz);
+                    ax = fmaf(f, dx, ax);
+                    ay = fmaf(f, dy, ay);
+                    az = fmaf(f, dz, az);
+                    jx = fmaf(-f, dx, rotate_down(jx));
+                    jy = fmaf(-f, dy, rotate_down(jy));
+                    jz = fmaf(-f, dz, rotate_down(jz));
+                }
+                // after 64 rotations lane l holds source (l + 63) mod 64
+                const int sid = st * 64 + ((lane + 63) & 63);
+                jpart[wv][0][sid] = jx;
+                jpart[wv][1][sid] = jy;
+                jpart[wv][2][sid] = jz;
+            }
+            __syncthreads();
+            const int j = j0 + threadIdx.x;
+            if (j < N) {
+                for (int c = 0; c < 3; ++c) {
+                    const float v = ((jpart[0][c][threadIdx.x] + jpart[1][c][threadIdx.x]) +
+                                     jpart[2][c][threadIdx.x]) + jpart[3][c][threadIdx.x];
+                    atomicAdd(&acc_fix[(long long)c * Npad + j], to_fixed((double)v, kSymScale, &ctl->status));
+                }
+            }
+        }
+        sx += (double)ax;
+        sy += (double)ay;
+        sz += (double)az;
+    }
+    if (i < N) {
+        atomicAdd(&acc_fix[i], to_fixed(sx, kSymScale, &ctl->status));
+        atomicAdd(&acc_fix[(long long)Npad + i], to_fixed(sy, kSymScale, &ctl->status));
+        atomicAdd(&acc_fix[2 * (long long)Npad + i], to_fixed(sz, kSymScale, &ctl->status));
+    }
+}
+
+// Per ion: total of the pair sums, then the terms of pair_epilogue; clears
+// the accumulators (every slot of the Npad planes).
+__global__ __launch_bounds__(256) void pair_sym_epilogue(const float* __restrict__ xs,
+                                                         unsigned long long* __restrict__ acc_fix,
+                                                         float* __restrict__ acc, PairArgs p,
+                                                         DustSet ds, Ctl* __restrict__ ctl)
+{
+    __shared__ double red[4][kMaxDust][3];
+    const int Npad = p.Npad;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const bool live = i < p.N;
+    const float xi = xs[i], yi = xs[Npad + i], zi = xs[2 * Npad + i];
+    double s[3];
+    for (int c = 0; c < 3; ++c) {
+        unsigned long long* a = &acc_fix[(long long)c * Npad + i];
+        s[c] = live ? from_fixed(*a, kSymScale) : 0.0;
+        *a = 0ull;
+    }
+    pair_epilogue<256>(xi, yi, zi, i, live, p.Cd * s[0], p.Cd * s[1], p.Cd * s[2], true, p, ds, ctl,
+                       acc, acc + Npad, acc + 2 * Npad, red);
+}
+
+}  // namespace odk

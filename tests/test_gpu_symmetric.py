@@ -1,0 +1,89 @@
+"""GPU parity of the symmetric all-pairs kernel (each unordered pair once,
+reactions applied to the sources) against the FP64 oracle, plus its
+agreement with the one-sided kernel, determinism and selection rules."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2205_06557_amd import workloads as W
+from tests.gpu_util import accel_errors, say, shadow_step
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2205_06557_amd import binding
+    binding.lib()
+    return binding
+
+
+@pytest.mark.parametrize("n_ions", [2000, 257, 1037, 4096])
+def test_shadowed_steps_symmetric(B, n_ions):
+    w = W.single_grain_small().with_(n_ions=n_ions)
+    say("symmetric kernel, N", n_ions)
+    with B.System(w) as s:
+        s.set_pair_kernel(B.PAIR_SYMMETRIC)
+        assert s.pair_kernel() == B.PAIR_SYMMETRIC and s.pair_split() == 1
+        o = O.Oracle(w)
+        for k in range(2):
+            say("  step", k, shadow_step(s, o, w))
+        s.step(30)
+        say("  after 30 free steps", shadow_step(s, o, w))
+
+
+def test_two_grains_symmetric(B):
+    w = W.two_grain_wake().with_(n_ions=5000)
+    with B.System(w) as s:
+        s.set_pair_kernel(B.PAIR_SYMMETRIC)
+        o = O.Oracle(w)
+        s.step(10)
+        say("two grains, symmetric", shadow_step(s, o, w))
+
+
+def test_symmetric_matches_one_sided(B):
+    w = W.single_grain_small().with_(n_ions=(1 << 17) + 77)
+    with B.System(w) as sym, B.System(w) as one:
+        assert sym.pair_kernel() == B.PAIR_SYMMETRIC          # chosen by size
+        one.set_pair_kernel(B.PAIR_ONE_SIDED)
+        sym.step(1)
+        one.step(1)
+        a_s = sym.accelerations().astype(np.float64).T
+        a_o = one.accelerations().astype(np.float64).T
+        l2, p999, pmax = accel_errors(a_s, a_o)
+        say("symmetric vs one-sided at 2^17+77:", l2, p999, pmax)
+        assert l2 < 1e-6 and p999 < 3e-6
+        Fs, Fo = sym.forces(0), one.forces(0)
+        assert np.allclose(Fs[0, 0], Fo[0, 0], rtol=1e-9, atol=0)   # Eq. (1) sums do not use the pair sums
+
+
+def test_symmetric_bitwise_reproducible(B):
+    w = W.single_grain_small().with_(n_ions=(1 << 16) + 37)
+    res = []
+    for _ in range(2):
+        with B.System(w) as s:
+            assert s.pair_kernel() == B.PAIR_SYMMETRIC
+            s.step(8)
+            x, v, q, _ = s.get_state()
+            res.append((x, v, q, s.accelerations()))
+    for a, b in zip(*res):
+        assert np.array_equal(a, b)
+
+
+def test_selection_rules(B):
+    small = W.single_grain_small()
+    with B.System(small) as s:
+        assert s.pair_kernel() == B.PAIR_ONE_SIDED
+        s.set_pair_kernel(B.PAIR_SYMMETRIC)
+        with pytest.raises(B.OdError):
+            s.set_pair_split(2)
+        s.set_pair_split(1)
+        s.set_pair_kernel(B.PAIR_AUTO)
+        assert s.pair_kernel() == B.PAIR_ONE_SIDED
+    with B.System(small, precision=B.PREC_FP64) as s:
+        with pytest.raises(B.OdError):
+            s.set_pair_kernel(B.PAIR_SYMMETRIC)
+    tp = small.with_(flags=W.FLAG_NO_ION_ION)
+    with B.System(tp) as s:
+        with pytest.raises(B.OdError):
+            s.set_pair_kernel(B.PAIR_SYMMETRIC)
