@@ -296,9 +296,17 @@ od_status od_batch_set_config(od_batch* b, int32_t persistent, int32_t jsplit, i
 od_status od_batch_get_config(od_batch* b, int32_t* persistent, int32_t* jsplit, int64_t* split_max_n,
                               int32_t* n_items);
 
-/* Times the pair phase for each candidate configuration (persistent or not;
- * jsplit 1, 2, 4; split_max_n 2^15, 2^16), keeps the fastest, and returns its
- * time in *best_ms.  With cache_path (a text file of one JSON object per
+/* Pair kernel of the batch: OD_PAIR_ONE_SIDED (the default; OD_PAIR_AUTO
+ * selects it too) or OD_PAIR_SYMMETRIC, each unordered pair once with int64
+ * fixed-point totals (see od_set_pair_kernel); a member then equals the same
+ * system run alone with OD_PAIR_SYMMETRIC bit for bit, and the persistent,
+ * jsplit and split_max_n settings do not apply.  Drops a captured graph. */
+od_status od_batch_set_pair_kernel(od_batch* b, int32_t kind);
+od_status od_batch_get_pair_kernel(od_batch* b, int32_t* kind);
+
+/* Times the pair phase for each candidate configuration (one-sided:
+ * persistent or not, jsplit 1, 2, 4, split_max_n 2^15, 2^16; and the
+ * symmetric kernel), keeps the fastest, and returns its time in *best_ms.  With cache_path (a text file of one JSON object per
  * line, keyed by GPU architecture, CU count and the histogram of log2 N of
  * the systems) a cached choice is reused and a new one appended.  The
  * systems' state is unchanged. */

@@ -339,11 +339,14 @@ def _batch_lib():
         L.od_batch_get_kernel_times.argtypes = [vp, dp, i64p]
         L.od_batch_get_confinement.argtypes = [vp, i32, dp, dp, C.POINTER(C.c_int32),
                                                C.POINTER(C.c_int32)]
+        L.od_batch_set_pair_kernel.argtypes = [vp, i32]
+        L.od_batch_get_pair_kernel.argtypes = [vp, C.POINTER(C.c_int32)]
         for name in ("od_init_batch", "od_batch_set_config", "od_batch_get_config", "od_batch_autotune",
                      "od_batch_set_graph", "od_step_batch", "od_batch_sync", "od_batch_get_sizes",
                      "od_batch_get_dust_charges", "od_batch_get_dust_forces", "od_batch_get_state",
                      "od_batch_set_state", "od_batch_get_accelerations", "od_batch_get_step_events",
-                     "od_batch_set_timing", "od_batch_get_kernel_times", "od_batch_get_confinement"):
+                     "od_batch_set_timing", "od_batch_get_kernel_times", "od_batch_get_confinement",
+                     "od_batch_set_pair_kernel", "od_batch_get_pair_kernel"):
             getattr(L, name).restype = C.c_int
         _batch_sigs = True
     return L
@@ -457,6 +460,14 @@ class Batch:
 
     def confinement(self, s: int):
         return _confinement(lambda *a: _batch_lib().od_batch_get_confinement(self._h, s, *a))
+
+    def set_pair_kernel(self, kind: int):
+        _check(_batch_lib().od_batch_set_pair_kernel(self._h, int(kind)))
+
+    def pair_kernel(self) -> int:
+        k = C.c_int32(0)
+        _check(_batch_lib().od_batch_get_pair_kernel(self._h, C.byref(k)))
+        return k.value
 
     def events(self, s: int):
         N = int(self.ws[s].n_ions)

@@ -11,6 +11,7 @@
 #pragma once
 
 #include "kernels.hpp"
+#include "pairsym.hpp"
 
 namespace odk {
 
@@ -76,6 +77,57 @@ void pair_batch_kernel(const float* __restrict__ xs,
                                   o + plane, o + 2 * plane, split == 0, tile, red);
         if (!persistent) break;
     }
+}
+
+// Symmetric pair sums of the batch (each unordered pair once, see
+// pairsym.hpp): item = (system, target tile row, source tile run); int64
+// fixed-point totals in fix (planes `plane` apart, system at its offset).
+struct SymBatchItem {
+    int sys, I, J0, J1;
+};
+
+template <int BLOCK, int TJ>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8, 8)))
+void pair_sym_batch_kernel(const float* __restrict__ xs, long long plane, const SysDesc* sys,
+                           Ctl* __restrict__ ctls, const SymBatchItem* __restrict__ items,
+                           unsigned long long* __restrict__ fix)
+{
+    static_assert(BLOCK == TJ, "square tiles");
+    __shared__ float4 src[4][128];
+    __shared__ float jpart[4][3][BLOCK];
+    const SymBatchItem it = items[blockIdx.x];
+    const int s = uniform_int(it.sys);
+    const long long off = sys[s].off;
+    const float* X = xs + off;
+    sym_item<BLOCK>(X, X + plane, X + 2 * plane, sys[s].pa.N, uniform_int(it.I), uniform_int(it.J0),
+                    uniform_int(it.J1), fix + off, plane, &ctls[s].status, src, jpart);
+}
+
+// Per ion of every system (block b belongs to system blk_sys[b]): converts
+// the fixed-point totals, adds the pair_epilogue terms, clears the totals.
+__global__ __launch_bounds__(256) void pair_sym_batch_epilogue(const float* __restrict__ xs,
+                                                               float* __restrict__ acc, long long plane,
+                                                               unsigned long long* __restrict__ fix,
+                                                               const SysDesc* sys, Ctl* __restrict__ ctls,
+                                                               const int* __restrict__ blk_sys)
+{
+    __shared__ double red[4][kMaxDust][3];
+    const int s = uniform_int(blk_sys[blockIdx.x]);
+    const SysDesc& S = sys[s];
+    const long long off = S.off;
+    const int i = (blockIdx.x - S.blk0) * 256 + threadIdx.x;
+    const bool live = i < S.pa.N;
+    const float* X = xs + off;
+    const float xi = X[i], yi = X[plane + i], zi = X[2 * plane + i];
+    double v[3];
+    for (int c = 0; c < 3; ++c) {
+        unsigned long long* a = &fix[c * plane + off + i];
+        v[c] = live ? from_fixed(*a, kSymScale) : 0.0;
+        *a = 0ull;
+    }
+    float* o = acc + off;
+    pair_epilogue<256>(xi, yi, zi, i, live, S.pa.Cd * v[0], S.pa.Cd * v[1], S.pa.Cd * v[2], true, S.pa,
+                       S.ds, ctls + s, o, o + plane, o + 2 * plane, red);
 }
 
 // Push of the whole batch: block b belongs to system blk_sys[b].

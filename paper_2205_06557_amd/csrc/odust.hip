@@ -176,16 +176,24 @@ void free_sym(od_system* s)
     s->sym = false;
 }
 
-// Work items of the symmetric sum: runs of at most C source tiles J >= I of
-// each target tile row I, C chosen for about kSymItemsTarget items; longest
-// first, so that the short ones fill the tail.
-std::vector<odk::SymItem> sym_items(int T)
+// Work items of the symmetric sum of one system of T tiles: runs of at most
+// C source tiles J >= I of each target tile row I, C chosen for about
+// kSymItemsTarget items.  The split depends on T only, so a system's sums are
+// grouped the same way alone and in a batch.
+std::vector<odk::SymItem> sym_items_of(int T)
 {
     const double pairs = 0.5 * (double)T * (T + 1);
     const int C = (int)std::max(1.0, std::ceil(pairs / kSymItemsTarget));
     std::vector<odk::SymItem> v;
     for (int I = 0; I < T; ++I)
         for (int J0 = I; J0 < T; J0 += C) v.push_back({I, J0, std::min(J0 + C, T), 0});
+    return v;
+}
+
+// Longest items first, so that the short ones fill the tail.
+std::vector<odk::SymItem> sym_items(int T)
+{
+    std::vector<odk::SymItem> v = sym_items_of(T);
     std::stable_sort(v.begin(), v.end(), [](const odk::SymItem& a, const odk::SymItem& b) {
         return a.J1 - a.J0 > b.J1 - b.J0;
     });

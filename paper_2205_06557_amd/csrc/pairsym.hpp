@@ -52,23 +52,21 @@ __device__ __forceinline__ float rotate_down(float v)
                                                               0xf, true));
 }
 
+// One work item of one system (positions X, Y, Z; N ions): target tile row
+// I against source tiles [J0, J1).  Reactions go to fix[c * stride + j],
+// the targets' sums to fix[c * stride + i] (indices local to the system).
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8, 8)))
-void pair_sym_kernel(const float* __restrict__ xs, int Npad, int N, const SymItem* __restrict__ items,
-                     unsigned long long* __restrict__ acc_fix, Ctl* __restrict__ ctl)
+__device__ __forceinline__ void sym_item(const float* __restrict__ X, const float* __restrict__ Y,
+                                         const float* __restrict__ Z, int N, int I, int J0, int J1,
+                                         unsigned long long* __restrict__ fix, long long stride,
+                                         int* status, float4 (*src)[128], float (*jpart)[3][BLOCK])
 {
     static_assert(BLOCK == 256, "four waves of 64");
-    __shared__ float4 src[4][128];          // sub-tiles of 64 sources, each stored twice
-    __shared__ float jpart[4][3][BLOCK];    // reactions per wave
-    const float* X = xs;
-    const float* Y = xs + Npad;
-    const float* Z = xs + 2 * Npad;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const SymItem it = items[blockIdx.x];
-    const int i = it.I * BLOCK + threadIdx.x;
+    const int i = I * BLOCK + threadIdx.x;
     const float xi = X[i], yi = Y[i], zi = Z[i];
     double sx = 0.0, sy = 0.0, sz = 0.0;
-    for (int J = it.J0; J < it.J1; ++J) {
+    for (int J = J0; J < J1; ++J) {
         const int j0 = J * BLOCK;
         __syncthreads();
         {
@@ -79,7 +77,7 @@ void pair_sym_kernel(const float* __restrict__ xs, int Npad, int N, const SymIte
         }
         __syncthreads();
         float ax = 0.0f, ay = 0.0f, az = 0.0f;
-        if (J == it.I) {
+        if (J == I) {
             for (int k = 0; k < BLOCK; ++k) {
                 const float4 q = src[k >> 6][k & 63];
                 const float dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
@@ -117,7 +115,7 @@ void pair_sym_kernel(const float* __restrict__ xs, int Npad, int N, const SymIte
                 for (int c = 0; c < 3; ++c) {
                     const float v = ((jpart[0][c][threadIdx.x] + jpart[1][c][threadIdx.x]) +
                                      jpart[2][c][threadIdx.x]) + jpart[3][c][threadIdx.x];
-                    atomicAdd(&acc_fix[(long long)c * Npad + j], to_fixed((double)v, kSymScale, &ctl->status));
+                    atomicAdd(&fix[c * stride + j], to_fixed((double)v, kSymScale, status));
                 }
             }
         }
@@ -126,10 +124,22 @@ void pair_sym_kernel(const float* __restrict__ xs, int Npad, int N, const SymIte
         sz += (double)az;
     }
     if (i < N) {
-        atomicAdd(&acc_fix[i], to_fixed(sx, kSymScale, &ctl->status));
-        atomicAdd(&acc_fix[(long long)Npad + i], to_fixed(sy, kSymScale, &ctl->status));
-        atomicAdd(&acc_fix[2 * (long long)Npad + i], to_fixed(sz, kSymScale, &ctl->status));
+        atomicAdd(&fix[i], to_fixed(sx, kSymScale, status));
+        atomicAdd(&fix[stride + i], to_fixed(sy, kSymScale, status));
+        atomicAdd(&fix[2 * stride + i], to_fixed(sz, kSymScale, status));
     }
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8, 8)))
+void pair_sym_kernel(const float* __restrict__ xs, int Npad, int N, const SymItem* __restrict__ items,
+                     unsigned long long* __restrict__ acc_fix, Ctl* __restrict__ ctl)
+{
+    __shared__ float4 src[4][128];          // sub-tiles of 64 sources, each stored twice
+    __shared__ float jpart[4][3][BLOCK];    // reactions per wave
+    const SymItem it = items[blockIdx.x];
+    sym_item<BLOCK>(xs, xs + Npad, xs + 2 * Npad, N, it.I, it.J0, it.J1, acc_fix, Npad, &ctl->status,
+                    src, jpart);
 }
 
 // Per ion: total of the pair sums, then the terms of pair_epilogue; clears

@@ -87,3 +87,49 @@ def test_selection_rules(B):
     with B.System(tp) as s:
         with pytest.raises(B.OdError):
             s.set_pair_kernel(B.PAIR_SYMMETRIC)
+
+
+def _batch_systems():
+    base = W.single_grain_small()
+    return [base.with_(n_ions=1500, system_id=0),
+            base.with_(n_ions=4099, system_id=1, mach=0.6, nu_in=0.2 * base.wpi),
+            base.with_(n_ions=700, system_id=2, flags=W.FLAG_NO_ION_ION),
+            W.two_grain_wake().with_(n_ions=2600, system_id=3, seed=3)]
+
+
+def test_batch_symmetric_equals_single(B):
+    ws = _batch_systems()
+    steps = 9
+    with B.Batch(ws) as b:
+        b.set_pair_kernel(B.PAIR_SYMMETRIC)
+        assert b.pair_kernel() == B.PAIR_SYMMETRIC
+        b.step(steps)
+        b.sync()
+        got = [(*b.get_state(s)[:3], b.forces(s, 0), b.accelerations(s)) for s in range(len(ws))]
+    for s, w in enumerate(ws):
+        with B.System(w) as one:
+            if not (int(w.flags) & W.FLAG_NO_ION_ION):
+                one.set_pair_kernel(B.PAIR_SYMMETRIC)
+            one.step(steps)
+            x, v, q, _ = one.get_state()
+            ref = (x, v, q, one.forces(0), one.accelerations())
+        for a, r in zip(got[s], ref):
+            assert np.array_equal(np.asarray(a), np.asarray(r)), (s, w.name)
+
+
+def test_batch_symmetric_graph_and_oracle(B):
+    ws = _batch_systems()
+    with B.Batch(ws) as eager, B.Batch(ws) as graph:
+        for b in (eager, graph):
+            b.set_pair_kernel(B.PAIR_SYMMETRIC)
+        graph.set_graph(4)
+        eager.step(8)
+        graph.step(8)
+        eager.sync()
+        graph.sync()
+        for s in range(len(ws)):
+            for a, r in zip(eager.get_state(s)[:3], graph.get_state(s)[:3]):
+                assert np.array_equal(a, r)
+        m = B.BatchMember(eager, 1)
+        o = O.Oracle(ws[1])
+        say("batch member, symmetric", shadow_step(m, o, ws[1]))
