@@ -165,6 +165,7 @@ def batch_bench(args):
     b = B.Batch(ws)
     tune_ms = b.autotune(None)
     cfg = b.config()
+    cfg["pair_kernel"] = "symmetric" if b.pair_kernel() == B.PAIR_SYMMETRIC else "one-sided"
     graph = 10 if K % 10 == 0 else 0
     b.set_graph(graph)
     b.step(max(args.warmup, 1) * (graph or 1))

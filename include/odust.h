@@ -225,10 +225,14 @@ od_status od_get_accelerations(od_system* sys, void* a_host);
  * OD_PAIR_ONE_SIDED evaluates every ordered pair (one target per lane, all
  * sources); OD_PAIR_SYMMETRIC evaluates each unordered pair once and applies
  * the reaction to the source (Newton's third law of the screened Coulomb
- * force), accumulating both sides in int64 fixed point (resolution 2^-20 of
- * the raw pair sums), so the result does not depend on scheduling and is
- * bitwise reproducible; it rounds differently from the one-sided kernel.
- * OD_PAIR_AUTO (the default) takes the symmetric kernel from 2^16 ions.
+ * force), accumulating both sides in int64 fixed point (a power of two set
+ * from the ion density n per r_De^3, 2^(27 - (2/3) log2 n), so that the
+ * resolution is about 1e-8 of a typical sum), so the result does not depend
+ * on scheduling and is bitwise reproducible; it rounds differently from the
+ * one-sided kernel.  A pair closer than about 4e-6 of the mean ion spacing
+ * overflows the range and is reported as OD_ENUMERIC.
+ * OD_PAIR_AUTO (the default) takes the symmetric kernel, which is the faster
+ * one at every size (1.6x at 2^18 and 2.4x at 2^12 ions on MI355X).
  * The symmetric kernel needs 24 bytes per ion of accumulators.  FP64 systems
  * and the test-particle mode always use the one-sided kernel; a cutoff
  * (od_set_cutoff) takes precedence over either.  od_get_pair_kernel reports
@@ -274,7 +278,8 @@ od_status od_get_kernel_times(od_system* sys, double* ms_host, int64_t* launches
  * step phase for all systems, the pair forces as a cost-ordered work list
  * pulled by a persistent grid, optionally captured as a HIP graph of several
  * steps.  Results of a system equal those of the same system run alone
- * bit for bit when its pair sum is not split (see od_batch_set_config).
+ * with the same pair kernel, bit for bit (for the one-sided kernel, when its
+ * pair sum is not split; see od_batch_set_config).
  * FP32 only (sim[s].precision must be OD_PREC_FP32).
  *   plasma_host[n_systems], sim_host[n_systems]: per-system parameters;
  *   dust_host: all grains, system after system; n_dust_host[n_systems];
@@ -296,11 +301,11 @@ od_status od_batch_set_config(od_batch* b, int32_t persistent, int32_t jsplit, i
 od_status od_batch_get_config(od_batch* b, int32_t* persistent, int32_t* jsplit, int64_t* split_max_n,
                               int32_t* n_items);
 
-/* Pair kernel of the batch: OD_PAIR_ONE_SIDED (the default; OD_PAIR_AUTO
- * selects it too) or OD_PAIR_SYMMETRIC, each unordered pair once with int64
- * fixed-point totals (see od_set_pair_kernel); a member then equals the same
- * system run alone with OD_PAIR_SYMMETRIC bit for bit, and the persistent,
- * jsplit and split_max_n settings do not apply.  Drops a captured graph. */
+/* Pair kernel of the batch: OD_PAIR_SYMMETRIC (the default; OD_PAIR_AUTO
+ * selects it too), each unordered pair once with int64 fixed-point totals
+ * (see od_set_pair_kernel), or OD_PAIR_ONE_SIDED.  The persistent, jsplit and
+ * split_max_n settings apply to the one-sided kernel only.  Drops a captured
+ * graph. */
 od_status od_batch_set_pair_kernel(od_batch* b, int32_t kind);
 od_status od_batch_get_pair_kernel(od_batch* b, int32_t* kind);
 

@@ -100,7 +100,8 @@ void pair_sym_batch_kernel(const float* __restrict__ xs, long long plane, const 
     const long long off = sys[s].off;
     const float* X = xs + off;
     sym_item<BLOCK>(X, X + plane, X + 2 * plane, sys[s].pa.N, uniform_int(it.I), uniform_int(it.J0),
-                    uniform_int(it.J1), fix + off, plane, &ctls[s].status, src, jpart);
+                    uniform_int(it.J1), fix + off, plane, sys[s].pa.sym_scale, &ctls[s].status, src,
+                    jpart);
 }
 
 // Per ion of every system (block b belongs to system blk_sys[b]): converts
@@ -122,7 +123,7 @@ __global__ __launch_bounds__(256) void pair_sym_batch_epilogue(const float* __re
     double v[3];
     for (int c = 0; c < 3; ++c) {
         unsigned long long* a = &fix[c * plane + off + i];
-        v[c] = live ? from_fixed(*a, kSymScale) : 0.0;
+        v[c] = live ? from_fixed(*a, S.pa.sym_scale) : 0.0;
         *a = 0ull;
     }
     float* o = acc + off;

@@ -71,6 +71,7 @@ struct PairArgs {
     double Cd;      // same in FP64
     double Kq;      // ion<-grain coupling per unit grain charge (e): 1/(4 pi n r_De^3)
     double Ez;      // homogeneous drive along z (dimensionless acceleration)
+    double sym_scale;   // fixed-point scale of the symmetric kernel's raw pair sums
     ConfField cf;   // confinement field, added to every ion when cf.on
 };
 

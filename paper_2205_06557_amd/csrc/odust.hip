@@ -40,7 +40,7 @@ constexpr int kPairTile = 256;
 constexpr int kPad = 256;
 constexpr int kReinjGrid = 2 * odk::kSlots;   // a multiple of the lost-list segments
 constexpr int kMaxSplitSingle = 4;             // source splits of one system's pair sum
-constexpr int kSymMinTiles = 256;             // all-pairs sum with each pair once from 2^16 ions
+constexpr int kSymMinTiles = 1;               // all-pairs sum with each pair once: at every size
 constexpr double kSymItemsTarget = 16384.0;    // work items of the symmetric sum
 constexpr int kConfNr = 32, kConfNz = 32;      // intervals of the confinement grid along r, z
 constexpr int kConfNodes = (kConfNr + 1) * (kConfNz + 1);
@@ -326,6 +326,12 @@ void derive_consts(const od_plasma& P, const od_sim& S, const od_dust* dust, int
     pa.C = (float)pa.Cd;
     pa.Kq = 1.0 / (4.0 * kPI * nl3);
     pa.Ez = Ez;
+    {
+        // fixed-point scale of the symmetric sums: 2^(27 - (2/3) log2 n), n ions per r_De^3
+        const double n_ions = (double)S.n_ions / Vt;
+        const double e = std::round(27.0 - (2.0 / 3.0) * std::log2(n_ions));
+        pa.sym_scale = std::ldexp(1.0, (int)std::min(40.0, std::max(10.0, e)));
+    }
 
     // face inflows per unit density (Appendix B), dimensionless
     auto face = [&](double m) { return m * normal_cdf(m / sig) + sig * normal_pdf(m / sig); };
@@ -532,7 +538,8 @@ od_status launch_step(od_system* s)
                 s->xs_sorted, s->idx_sorted, s->slab_start, (float*)s->a, s->pa, s->ca, s->ds, s->ctl);
         } else if (k == 0 && s->sym) {
             odk::pair_sym_kernel<kPairBlock><<<s->n_sym_items, kPairBlock, 0, s->stream>>>(
-                (const float*)s->x, (int)s->Npad, (int)s->N, s->sym_items, s->acc_fix, s->ctl);
+                (const float*)s->x, (int)s->Npad, (int)s->N, s->pa.sym_scale, s->sym_items, s->acc_fix,
+                s->ctl);
             odk::pair_sym_epilogue<<<(int)(s->Npad / 256), 256, 0, s->stream>>>(
                 (const float*)s->x, s->acc_fix, (float*)s->a, s->pa, s->ds, s->ctl);
         } else if (k == 0) {

@@ -25,9 +25,11 @@
 
 namespace odk {
 
-// Resolution of the accumulators of the raw sums (1 + r) e^-r / r^3 d:
-// 2^-20, range 2^43 (a single pair overflows only below 3e-7 r_De).
-constexpr double kSymScale = 1048576.0;
+// The accumulators hold the raw sums (1 + r) e^-r / r^3 d times a per-system
+// power of two, PairArgs::sym_scale, set by the host from the ion density so
+// that the resolution stays near 1e-8 of a typical sum (dominated by the
+// nearest neighbours, ~ n^(2/3)) while the int64 range keeps a margin of
+// about 1e13 for close pairs.
 
 struct SymItem {
     int I, J0, J1, pad_;
@@ -59,7 +61,8 @@ template <int BLOCK>
 __device__ __forceinline__ void sym_item(const float* __restrict__ X, const float* __restrict__ Y,
                                          const float* __restrict__ Z, int N, int I, int J0, int J1,
                                          unsigned long long* __restrict__ fix, long long stride,
-                                         int* status, float4 (*src)[128], float (*jpart)[3][BLOCK])
+                                         double scale, int* status, float4 (*src)[128],
+                                         float (*jpart)[3][BLOCK])
 {
     static_assert(BLOCK == 256, "four waves of 64");
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -115,7 +118,7 @@ __device__ __forceinline__ void sym_item(const float* __restrict__ X, const floa
                 for (int c = 0; c < 3; ++c) {
                     const float v = ((jpart[0][c][threadIdx.x] + jpart[1][c][threadIdx.x]) +
                                      jpart[2][c][threadIdx.x]) + jpart[3][c][threadIdx.x];
-                    atomicAdd(&fix[c * stride + j], to_fixed((double)v, kSymScale, status));
+                    atomicAdd(&fix[c * stride + j], to_fixed((double)v, scale, status));
                 }
             }
         }
@@ -124,22 +127,23 @@ __device__ __forceinline__ void sym_item(const float* __restrict__ X, const floa
         sz += (double)az;
     }
     if (i < N) {
-        atomicAdd(&fix[i], to_fixed(sx, kSymScale, status));
-        atomicAdd(&fix[stride + i], to_fixed(sy, kSymScale, status));
-        atomicAdd(&fix[2 * stride + i], to_fixed(sz, kSymScale, status));
+        atomicAdd(&fix[i], to_fixed(sx, scale, status));
+        atomicAdd(&fix[stride + i], to_fixed(sy, scale, status));
+        atomicAdd(&fix[2 * stride + i], to_fixed(sz, scale, status));
     }
 }
 
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8, 8)))
-void pair_sym_kernel(const float* __restrict__ xs, int Npad, int N, const SymItem* __restrict__ items,
-                     unsigned long long* __restrict__ acc_fix, Ctl* __restrict__ ctl)
+void pair_sym_kernel(const float* __restrict__ xs, int Npad, int N, double scale,
+                     const SymItem* __restrict__ items, unsigned long long* __restrict__ acc_fix,
+                     Ctl* __restrict__ ctl)
 {
     __shared__ float4 src[4][128];          // sub-tiles of 64 sources, each stored twice
     __shared__ float jpart[4][3][BLOCK];    // reactions per wave
     const SymItem it = items[blockIdx.x];
-    sym_item<BLOCK>(xs, xs + Npad, xs + 2 * Npad, N, it.I, it.J0, it.J1, acc_fix, Npad, &ctl->status,
-                    src, jpart);
+    sym_item<BLOCK>(xs, xs + Npad, xs + 2 * Npad, N, it.I, it.J0, it.J1, acc_fix, Npad, scale,
+                    &ctl->status, src, jpart);
 }
 
 // Per ion: total of the pair sums, then the terms of pair_epilogue; clears
@@ -157,7 +161,7 @@ __global__ __launch_bounds__(256) void pair_sym_epilogue(const float* __restrict
     double s[3];
     for (int c = 0; c < 3; ++c) {
         unsigned long long* a = &acc_fix[(long long)c * Npad + i];
-        s[c] = live ? from_fixed(*a, kSymScale) : 0.0;
+        s[c] = live ? from_fixed(*a, p.sym_scale) : 0.0;
         *a = 0ull;
     }
     pair_epilogue<256>(xi, yi, zi, i, live, p.Cd * s[0], p.Cd * s[1], p.Cd * s[2], true, p, ds, ctl,

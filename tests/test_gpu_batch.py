@@ -38,6 +38,7 @@ def _systems():
 
 def _run_single(B, w, steps, nsplit=1):
     with B.System(w) as s:
+        s.set_pair_kernel(B.PAIR_ONE_SIDED)
         s.set_pair_split(nsplit)
         s.step(steps)
         x, v, q, st = s.get_state()
@@ -45,7 +46,9 @@ def _run_single(B, w, steps, nsplit=1):
 
 
 def _run_batch(B, ws, steps, **cfg):
+    """The one-sided kernel with the given decomposition."""
     with B.Batch(ws) as b:
+        b.set_pair_kernel(B.PAIR_ONE_SIDED)
         graph = cfg.pop("graph", 0)
         if cfg:
             b.set_config(**cfg)
@@ -82,6 +85,8 @@ def test_scheduling_and_graph_replay_bitwise(B):
 def test_split_sums_close_to_unsplit(B):
     ws = _systems()
     with B.Batch(ws) as b1, B.Batch(ws) as b4:
+        for b in (b1, b4):
+            b.set_pair_kernel(B.PAIR_ONE_SIDED)
         b1.set_config(True, 1, 0)
         b4.set_config(True, 4, 1 << 20)
         for s in range(len(ws)):
@@ -98,6 +103,7 @@ def test_split_sums_close_to_unsplit(B):
 def test_batched_systems_match_oracle(B):
     ws = _systems()
     with B.Batch(ws) as b:
+        b.set_pair_kernel(B.PAIR_ONE_SIDED)
         b.set_config(True, 2, 1 << 20)
         b.step(3)
         for s in (0, 2, 6):
@@ -114,7 +120,8 @@ def test_autotune_keeps_state_and_caches(B, tmp_path):
         before = [b.get_state(s) for s in range(len(ws))]
         ms = b.autotune(cache)
         cfg = b.config()
-        say("autotune", ms, cfg)
+        kind = b.pair_kernel()
+        say("autotune", ms, cfg, "pair kernel", kind)
         assert ms > 0 and os.path.exists(cache)
         after = [b.get_state(s) for s in range(len(ws))]
         for x, y in zip(before, after):
@@ -126,4 +133,5 @@ def test_autotune_keeps_state_and_caches(B, tmp_path):
         ms2 = b2.autotune(cache)
         assert ms2 == pytest.approx(ms, rel=1e-6)
         assert b2.config()["jsplit"] == cfg["jsplit"]
+        assert b2.pair_kernel() == kind
         assert len(open(cache).read().strip().splitlines()) == 1

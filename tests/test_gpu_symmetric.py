@@ -44,7 +44,7 @@ def test_two_grains_symmetric(B):
 def test_symmetric_matches_one_sided(B):
     w = W.single_grain_small().with_(n_ions=(1 << 17) + 77)
     with B.System(w) as sym, B.System(w) as one:
-        assert sym.pair_kernel() == B.PAIR_SYMMETRIC          # chosen by size
+        assert sym.pair_kernel() == B.PAIR_SYMMETRIC          # the default
         one.set_pair_kernel(B.PAIR_ONE_SIDED)
         sym.step(1)
         one.step(1)
@@ -73,13 +73,16 @@ def test_symmetric_bitwise_reproducible(B):
 def test_selection_rules(B):
     small = W.single_grain_small()
     with B.System(small) as s:
-        assert s.pair_kernel() == B.PAIR_ONE_SIDED
-        s.set_pair_kernel(B.PAIR_SYMMETRIC)
+        assert s.pair_kernel() == B.PAIR_SYMMETRIC          # the default for FP32 with ion-ion forces
         with pytest.raises(B.OdError):
             s.set_pair_split(2)
         s.set_pair_split(1)
-        s.set_pair_kernel(B.PAIR_AUTO)
+        s.set_pair_kernel(B.PAIR_ONE_SIDED)
         assert s.pair_kernel() == B.PAIR_ONE_SIDED
+        s.set_pair_split(2)
+        assert s.pair_split() == 2
+        s.set_pair_kernel(B.PAIR_AUTO)
+        assert s.pair_kernel() == B.PAIR_SYMMETRIC and s.pair_split() == 1
     with B.System(small, precision=B.PREC_FP64) as s:
         with pytest.raises(B.OdError):
             s.set_pair_kernel(B.PAIR_SYMMETRIC)
