@@ -54,13 +54,13 @@ AVG_STEPS = 2000   # trailing steps averaged for the targets
 
 def chain_workload(x5: Sequence[float], n_ions: int, steps: int, seed: int, system_id: int,
                    q0: Optional[Sequence[float]] = None, n_discard: Optional[int] = None,
-                   dt_wpi: float = DT_WPI) -> W.Workload:
+                   dt_wpi: float = DT_WPI, avg_steps: int = AVG_STEPS) -> W.Workload:
     """The 8-grain vertical chain for one input point: grains of radius a on the
     axis at z_k = (k - 3.5) d, cylinder R = 3 r_De, H = 7 d + 5 r_De, argon at
     T_e = 1 eV, n = 1e14 m^-3, self-consistent charging, dt = dt_wpi/omega_pi
     (0.04 by default: the grain charging time is ~70/omega_pi, so a 6,000-step
     run spans ~3.4 charging times).  q0: initial charges (C), default 0;
-    n_discard: default steps - AVG_STEPS."""
+    n_discard: default steps - avg_steps."""
     mach, a_um, d_l, nu_w, tt = (float(v) for v in x5)
     te = W.ev_to_kelvin(TE_EV)
     lam = W.debye_length(te, N_INF)
@@ -72,7 +72,7 @@ def chain_workload(x5: Sequence[float], n_ions: int, steps: int, seed: int, syst
     return W.Workload(Te=te, Ti=te / tt, n_inf=N_INF, m_i=W.M_ARGON, mach=mach, nu_in=nu_w * wpi,
                       E_ext=float("nan"), R=3 * lam, H=7 * d + 5 * lam, dt=dt_wpi / wpi,
                       n_ions=int(n_ions), n_steps=int(steps),
-                      n_discard=int(max(steps - AVG_STEPS, 0) if n_discard is None else n_discard),
+                      n_discard=int(max(steps - avg_steps, 0) if n_discard is None else n_discard),
                       seed=seed,
                       system_id=system_id, charge_mode=W.CHARGE_CONSISTENT, dust=dust,
                       name=f"chain8 {x5}")
@@ -108,10 +108,10 @@ def oml_charge(x5) -> float:
 
 def run_plain(X: np.ndarray, n_ions: int, steps: int, seed: int, start: str = "oml",
               q0: Optional[np.ndarray] = None, batch_size: int = 512, graph: int = 10,
-              log=None) -> np.ndarray:
+              log=None, avg_steps: int = AVG_STEPS) -> np.ndarray:
     """Runs the full method for every input row (batched) and returns the
     normalised targets [n, 16]: time-averaged charge and total axial force
-    (Eqs. (1)-(4) summed) of each grain over the last AVG_STEPS steps.
+    (Eqs. (1)-(4) summed) of each grain over the last avg_steps steps.
     start: "oml" (isolated-grain floating charge), "zero", or "given" (q0 [n, 8] in C)."""
     from . import binding as B
     n = X.shape[0]
@@ -126,7 +126,7 @@ def run_plain(X: np.ndarray, n_ions: int, steps: int, seed: int, start: str = "o
                 q = list(q0[r])
             else:
                 q = None
-            ws.append(chain_workload(X[r], n_ions, steps, seed, r, q))
+            ws.append(chain_workload(X[r], n_ions, steps, seed, r, q, avg_steps=avg_steps))
         t0 = time.time()
         b = B.Batch(ws)
         b.autotune(None)
@@ -217,27 +217,31 @@ def charge_trace(x5, n_ions: int, steps: int, seed: int, q0, block: int = 200):
 
 
 def generate(out: str, tag: str, total: int, start: int, count: int, n_ions: int, steps: int,
-             seed: int, run_seed: int):
+             seed: int, run_seed: int, avg_steps: int = AVG_STEPS):
     """Rows [start, start + count) of the sweep of `total` inputs (stream `seed`),
     run with the full method (random stream `run_seed`); saved as DIR/TAG_START.npz."""
     os.makedirs(out, exist_ok=True)
     X = sweep_inputs(total, seed)[start:start + count]
     t0 = time.time()
-    print(f"[surrogate] {tag}: rows {start}..{start + count - 1}, N={n_ions}, {steps} steps", flush=True)
-    T = run_plain(X, n_ions, steps, seed=run_seed, log=lambda m: print(m, flush=True))
+    print(f"[surrogate] {tag}: rows {start}..{start + count - 1}, N={n_ions}, {steps} steps, "
+          f"averages over the last {avg_steps}", flush=True)
+    T = run_plain(X, n_ions, steps, seed=run_seed, log=lambda m: print(m, flush=True), avg_steps=avg_steps)
     np.savez(os.path.join(out, f"{tag}_{start:05d}.npz"), X=X, T=T, n_ions=n_ions, steps=steps,
-             seconds=time.time() - t0)
+             avg_steps=avg_steps, seconds=time.time() - t0)
     print(f"[surrogate] {tag}: done in {time.time() - t0:.1f} s", flush=True)
 
 
-def _load(data: str, tag: str):
+def _load(data: str, tag: str, with_meta: bool = False):
     fs = sorted(f for f in os.listdir(data) if f.startswith(tag + "_") and f.endswith(".npz"))
-    Xs, Ts = [], []
+    Xs, Ts, meta = [], [], {}
     for f in fs:
         z = np.load(os.path.join(data, f))
         Xs.append(z["X"])
         Ts.append(z["T"])
-    return np.concatenate(Xs), np.concatenate(Ts)
+        meta = {"n_ions": int(z["n_ions"]), "steps": int(z["steps"]),
+                "avg_steps": int(z["avg_steps"]) if "avg_steps" in z.files else AVG_STEPS}
+    X, T = np.concatenate(Xs), np.concatenate(Ts)
+    return (X, T, meta) if with_meta else (X, T)
 
 
 def evaluate(data: str, out: str, epochs: int, eval_ions: int, eval_steps: int, seed: int = 11):
@@ -249,12 +253,12 @@ def evaluate(data: str, out: str, epochs: int, eval_ions: int, eval_steps: int, 
     def log(m):
         print(m, flush=True)
 
-    X, T = _load(data, "train")
+    X, T, meta = _load(data, "train", with_meta=True)
     Xt, Ta = _load(data, "testa")
     Xt2, Tb = _load(data, "testb")
     assert np.array_equal(Xt, Xt2)
     res = {"train_rows": int(len(X)), "test_rows": int(len(Xt)), "dt_wpi": DT_WPI,
-           "avg_steps": AVG_STEPS}
+           "run_n_ions": meta["n_ions"], "run_steps": meta["steps"], "avg_steps": meta["avg_steps"]}
     t1 = time.time()
     sur = Surrogate.train(X, T, epochs=epochs, seed=seed)
     res["train_s"] = time.time() - t1
@@ -284,7 +288,7 @@ def evaluate(data: str, out: str, epochs: int, eval_ions: int, eval_steps: int, 
     q_oml = oml_charge(x5)
     log("[surrogate] warm-start study: reference run")
     ref_tr, ref_s = charge_trace(x5, eval_ions, eval_steps, seed + 5, Qp[0])
-    q_ref = ref_tr[-AVG_STEPS:].mean(axis=0)
+    q_ref = ref_tr[-eval_steps // 2:].mean(axis=0)
     ws = {"x": x5.tolist(), "n_ions": eval_ions, "steps": eval_steps, "q_ref_e": (q_ref / W.QE).tolist(),
           "surrogate_q_e": (Qp[0] / W.QE).tolist(), "oml_q_e": q_oml / W.QE,
           "surrogate_q_err_vs_ref": float(np.max(np.abs(Qp[0] / q_ref - 1))),
@@ -324,6 +328,7 @@ def main(argv=None):
     g.add_argument("--steps", type=int, default=6000)
     g.add_argument("--seed", type=int, default=11)
     g.add_argument("--run-seed", type=int, default=11)
+    g.add_argument("--avg-steps", type=int, default=AVG_STEPS)
     e = sub.add_parser("evaluate")
     e.add_argument("--data", required=True)
     e.add_argument("--out", required=True)
@@ -332,7 +337,8 @@ def main(argv=None):
     e.add_argument("--eval-steps", type=int, default=10000)
     a = ap.parse_args(argv)
     if a.cmd == "generate":
-        generate(a.out, a.tag, a.total, a.start, a.count, a.n_ions, a.steps, a.seed, a.run_seed)
+        generate(a.out, a.tag, a.total, a.start, a.count, a.n_ions, a.steps, a.seed, a.run_seed,
+                 a.avg_steps)
     else:
         evaluate(a.data, a.out, a.epochs, a.eval_ions, a.eval_steps)
 
