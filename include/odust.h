@@ -174,16 +174,18 @@ od_status od_get_units(od_system* sys, double* units_host);
  * Eq. (1) stay complete.  Distances in m; r_cut <= 0 returns to the
  * all-pairs sum.  FP32 systems only (OD_EINVAL otherwise); needs
  * 0 <= r_switch < r_cut.  Each step then sorts the ions into slabs along z
- * (width >= r_cut, at most 1024 slabs) and evaluates, for every block of 256
- * sorted ions, only the sources of its slabs and their two neighbours.
- * Allocates the sort buffers (about 20 bytes per ion plus 4 bytes per slab
+ * (width about r_cut / 4, at most 1024 slabs) and evaluates each pair of
+ * blocks of 256 sorted ions within reach once (both reactions, int64 fixed
+ * point as the symmetric all-pairs kernel).
+ * Allocates the sort buffers (about 44 bytes per ion plus 4 bytes per slab
  * and block of 256 ions) with the system's allocator; synchronises the
  * system's stream. */
 od_status od_set_cutoff(od_system* sys, double r_switch, double r_cut);
 
 /* Cutoff bookkeeping of the last step: *nslab slabs and *pairs_evaluated,
- * the ion pairs the cutoff kernel evaluated (targets x staged sources,
- * padding included).  OD_ESTATE without a cutoff.  Synchronises. */
+ * the ordered ion pairs the cutoff kernel covered (each pair of 256-ion
+ * blocks counted both ways, padding included).  OD_ESTATE without a cutoff.
+ * Synchronises. */
 od_status od_get_cutoff_info(od_system* sys, int32_t* nslab, int64_t* pairs_evaluated);
 
 /* Confinement field of a system created with OD_FLAG_CONFINEMENT (Appendix A).

@@ -101,7 +101,7 @@ void pair_sym_batch_kernel(const float* __restrict__ xs, long long plane, const 
     const float* X = xs + off;
     sym_item<BLOCK>(X, X + plane, X + 2 * plane, sys[s].pa.N, uniform_int(it.I), uniform_int(it.J0),
                     uniform_int(it.J1), fix + off, plane, sys[s].pa.sym_scale, &ctls[s].status, src,
-                    jpart);
+                    jpart, PlainPair{});
 }
 
 // Per ion of every system (block b belongs to system blk_sys[b]): converts

@@ -6,19 +6,25 @@
 // and the force is -d(phi S)/dr; S and S' vanish from r_cut on, so pairs
 // beyond the cutoff contribute exactly zero without a branch.
 //
-// Every step the ions are binned into slabs along z of width >= r_cut and
-// sorted by slab with a stable counting sort (so the order, and with it every
+// Every step the ions are binned into slabs along z (width w, about r_cut / 4)
+// and sorted by slab with a stable counting sort (so the order, and with it every
 // floating-point sum, is deterministic):
 //   slab_count_kernel    slab of each ion; per-block slab histogram
 //   slab_scan_kernel     per slab, exclusive scan over blocks; slab totals
 //   slab_start_kernel    exclusive scan of the slab totals
 //   slab_scatter_kernel  sorted copy of the positions and their ion indices
-// A block of 256 consecutive sorted targets then meets only the sources of
-// its own slabs and one slab on either side (pair_cut_kernel), and writes
+// Pairs are then taken once each (as in pairsym.hpp): a block of 256
+// consecutive sorted ions (tile I) meets the sorted tiles J = I .. J1 - 1,
+// where J1 ends at the last source of the slabs within `reach` =
+// ceil(r_cut / w) slabs above its own (pair_cut_kernel).  A pair within r_cut
+// with its lower member in tile I has its upper member there, since sorted
+// order puts it at most `reach` slabs higher.  The totals go to int64
+// fixed-point accumulators indexed by sorted slot; pair_cut_epilogue writes
 // the accelerations back to the ions' own slots.
 #pragma once
 
 #include "kernels.hpp"
+#include "pairsym.hpp"
 
 namespace odk {
 
@@ -27,6 +33,8 @@ constexpr int kMaxSlabs = 1024;
 struct CutArgs {
     int nslab;        // slabs along z
     int nblk;         // blocks of 256 ions (sort granularity)
+    int reach;        // slabs on either side that can hold a source within r_cut
+    int pad_;
     float z0;         // lower end of the domain, -H/2
     float inv_w;      // 1 / slab width
     float rsw;        // start of the switching interval
@@ -153,83 +161,70 @@ __global__ __launch_bounds__(256) void slab_scatter_kernel(const float* __restri
     }
 }
 
-// One switched pair term added to (ax, ay, az): f d with
-// f = e^-r [(1 + r) S - r S'] / r^3, i.e. -d(phi S)/dr / (C r); skip zeroes it.
-__device__ __forceinline__ void cut_pair(float xi, float yi, float zi, float4 q, float rsw,
-                                         float inv_sw, float dS_c, float& ax, float& ay, float& az,
-                                         bool skip)
+// The switched pair term as a functor for sym_item.
+struct SwitchedPair {
+    float rsw, inv_sw, dS_c;
+    __device__ __forceinline__ float operator()(float dx, float dy, float dz) const
+    {
+        const float kNegLog2e = -1.4426950408889634f;
+        const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        const float ri = __builtin_amdgcn_rsqf(r2);
+        const float r = r2 * ri;
+        const float e = __builtin_amdgcn_exp2f(r * kNegLog2e);
+        const float x = __builtin_amdgcn_fmed3f((r - rsw) * inv_sw, 0.0f, 1.0f);
+        const float x2 = x * x;
+        const float S = fmaf(x2 * x, fmaf(fmaf(-6.0f, x, 15.0f), x, -10.0f), 1.0f);
+        const float u = fmaf(-x, x, x);              // x (1 - x)
+        const float dS = dS_c * u * u;               // S'(r) = -30 x^2 (1 - x)^2 / (r_cut - r_sw)
+        const float g = fmaf(r, S, S) - r * dS;      // (1 + r) S - r S'
+        return (ri * ri * ri) * (e * g);
+    }
+};
+
+// Switched forces, each pair once: block b takes sorted tile I = b against
+// the tiles up to the end of the slabs within reach above its last ion; the
+// sums go to fix (planes Npad apart, sorted slots).
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8, 8)))
+void pair_cut_kernel(const float* __restrict__ xs_sorted, const int* __restrict__ start,
+                     unsigned long long* __restrict__ fix, PairArgs p, CutArgs c,
+                     Ctl* __restrict__ ctl)
 {
-    const float kNegLog2e = -1.4426950408889634f;
-    const float dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
-    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-    const float ri = __builtin_amdgcn_rsqf(r2);
-    const float r = r2 * ri;
-    const float e = __builtin_amdgcn_exp2f(r * kNegLog2e);
-    const float x = __builtin_amdgcn_fmed3f((r - rsw) * inv_sw, 0.0f, 1.0f);
-    const float x2 = x * x;
-    const float S = fmaf(x2 * x, fmaf(fmaf(-6.0f, x, 15.0f), x, -10.0f), 1.0f);
-    const float u = fmaf(-x, x, x);                  // x (1 - x)
-    const float dS = dS_c * u * u;                   // S'(r) = -30 x^2 (1 - x)^2 / (r_cut - r_sw)
-    const float g = fmaf(r, S, S) - r * dS;          // (1 + r) S - r S'
-    float f = (ri * ri * ri) * (e * g);
-    f = skip ? 0.0f : f;
-    ax = fmaf(f, dx, ax);
-    ay = fmaf(f, dy, ay);
-    az = fmaf(f, dz, az);
+    __shared__ float4 src[4][128];
+    __shared__ float jpart[4][3][BLOCK];
+    if (!p.ion_ion) return;
+    const int Npad = p.Npad, N = p.N;
+    const float* Z = xs_sorted + 2 * Npad;
+    const int I = blockIdx.x;
+    const int s_hi = slab_of_z(Z[min((I + 1) * BLOCK, N) - 1], c);
+    const int je = start[min(s_hi + c.reach + 1, c.nslab)];
+    const int J1 = (je + BLOCK - 1) / BLOCK;
+    const SwitchedPair pair{c.rsw, c.inv_sw, -30.0f * c.inv_sw};
+    sym_item<BLOCK>(xs_sorted, xs_sorted + Npad, Z, N, I, I, J1, fix, Npad, p.sym_scale, &ctl->status,
+                    src, jpart, pair);
 }
 
-// Forces with the cutoff: block b takes sorted targets [256 b, 256 b + 256)
-// against the sorted sources of slabs s_lo - 1 .. s_hi + 1, in tiles of TJ
-// (entries past the range are parked far away and contribute zero).
-template <int BLOCK, int TJ>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8, 8)))
-void pair_cut_kernel(const float* __restrict__ xs_sorted, const int* __restrict__ idx,
-                     const int* __restrict__ start, float* __restrict__ acc, PairArgs p,
-                     CutArgs c, DustSet ds, Ctl* __restrict__ ctl)
+// Per sorted slot: converts the totals, adds the pair_epilogue terms and
+// writes the acceleration to the ion's own slot; clears the totals.
+__global__ __launch_bounds__(256) void pair_cut_epilogue(const float* __restrict__ xs_sorted,
+                                                         const int* __restrict__ idx,
+                                                         unsigned long long* __restrict__ fix,
+                                                         float* __restrict__ acc, PairArgs p,
+                                                         DustSet ds, Ctl* __restrict__ ctl)
 {
-    __shared__ float4 tile[TJ];
-    __shared__ double red[BLOCK / 64][kMaxDust][3];
-    const int Npad = p.Npad, N = p.N;
-    const float* X = xs_sorted;
-    const float* Y = xs_sorted + Npad;
-    const float* Z = xs_sorted + 2 * Npad;
-    const int i0 = blockIdx.x * BLOCK;
-    const int i = i0 + threadIdx.x;
-    const bool live = i < N;
-    const float xi = X[i], yi = Y[i], zi = Z[i];
-    const int s_lo = slab_of_z(Z[i0], c);
-    const int s_hi = slab_of_z(Z[min(i0 + BLOCK, N) - 1], c);
-    const int jb = start[max(s_lo - 1, 0)];
-    const int je = start[min(s_hi + 2, c.nslab)];
-    const float rsw = c.rsw, inv_sw = c.inv_sw;
-    const float dS_c = -30.0f * inv_sw;
-    double sx = 0.0, sy = 0.0, sz = 0.0;
-    if (p.ion_ion) {
-        for (int j0 = jb; j0 < je; j0 += TJ) {
-            __syncthreads();
-            for (int t = threadIdx.x; t < TJ; t += BLOCK) {
-                const int j = j0 + t;
-                tile[t] = j < je ? make_float4(X[j], Y[j], Z[j], 0.0f)
-                                 : make_float4(1.0e18f, 1.0e18f, 1.0e18f, 0.0f);
-            }
-            __syncthreads();
-            float ax = 0.0f, ay = 0.0f, az = 0.0f;
-            if (i0 + BLOCK <= j0 || j0 + TJ <= i0) {
-#pragma unroll 4
-                for (int k = 0; k < TJ; ++k)
-                    cut_pair(xi, yi, zi, tile[k], rsw, inv_sw, dS_c, ax, ay, az, false);
-            } else {
-                const int kself = i - j0;      // the target's own entry
-                for (int k = 0; k < TJ; ++k)
-                    cut_pair(xi, yi, zi, tile[k], rsw, inv_sw, dS_c, ax, ay, az, k == kself);
-            }
-            sx += (double)ax;
-            sy += (double)ay;
-            sz += (double)az;
-        }
+    __shared__ double red[4][kMaxDust][3];
+    const int Npad = p.Npad;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const bool live = i < p.N;
+    const float xi = xs_sorted[i], yi = xs_sorted[Npad + i], zi = xs_sorted[2 * Npad + i];
+    double v[3];
+    for (int c = 0; c < 3; ++c) {
+        unsigned long long* a = &fix[(long long)c * Npad + i];
+        v[c] = live ? from_fixed(*a, p.sym_scale) : 0.0;
+        *a = 0ull;
     }
-    pair_epilogue<BLOCK>(xi, yi, zi, live ? idx[i] : 0, live, p.Cd * sx, p.Cd * sy, p.Cd * sz, true,
-                         p, ds, ctl, acc, acc + Npad, acc + 2 * Npad, red);
+    pair_epilogue<256>(xi, yi, zi, live ? idx[i] : 0, live, p.Cd * v[0], p.Cd * v[1], p.Cd * v[2], true,
+                       p, ds, ctl, acc, acc + Npad, acc + 2 * Npad, red);
 }
 
 }  // namespace odk

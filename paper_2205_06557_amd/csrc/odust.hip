@@ -114,6 +114,7 @@ struct od_system {
     int* table = nullptr;               // [nslab][nblk] per-block counts, then offsets
     int* slab_total = nullptr;          // [nslab]
     int* slab_start = nullptr;          // [nslab + 1]
+    unsigned long long* cut_fix = nullptr;  // [3][Npad] fixed-point sums by sorted slot
     // all-pairs sum with each pair evaluated once
     int pair_kind = OD_PAIR_AUTO;
     bool sym = false;
@@ -161,6 +162,8 @@ void free_cutoff(od_system* s)
     dev_free(s, s->table);
     dev_free(s, s->slab_total);
     dev_free(s, s->slab_start);
+    dev_free(s, s->cut_fix);
+    s->cut_fix = nullptr;
     s->xs_sorted = nullptr;
     s->idx_sorted = s->slab = s->table = s->slab_total = s->slab_start = nullptr;
     s->cut = false;
@@ -534,8 +537,10 @@ od_status launch_step(od_system* s)
             odk::slab_scatter_kernel<<<nb, 256, 0, s->stream>>>(
                 x, x + P, x + 2 * P, (int)s->N, s->ca, s->slab, s->table, s->slab_start, s->xs_sorted,
                 s->xs_sorted + P, s->xs_sorted + 2 * P, s->idx_sorted);
-            odk::pair_cut_kernel<kPairBlock, kPairTile><<<nb, kPairBlock, 0, s->stream>>>(
-                s->xs_sorted, s->idx_sorted, s->slab_start, (float*)s->a, s->pa, s->ca, s->ds, s->ctl);
+            odk::pair_cut_kernel<kPairBlock><<<nb, kPairBlock, 0, s->stream>>>(
+                s->xs_sorted, s->slab_start, s->cut_fix, s->pa, s->ca, s->ctl);
+            odk::pair_cut_epilogue<<<nb, 256, 0, s->stream>>>(s->xs_sorted, s->idx_sorted, s->cut_fix,
+                                                               (float*)s->a, s->pa, s->ds, s->ctl);
         } else if (k == 0 && s->sym) {
             odk::pair_sym_kernel<kPairBlock><<<s->n_sym_items, kPairBlock, 0, s->stream>>>(
                 (const float*)s->x, (int)s->Npad, (int)s->N, s->pa.sym_scale, s->sym_items, s->acc_fix,
@@ -773,7 +778,9 @@ od_status od_set_cutoff(od_system* s, double r_switch, double r_cut)
     if (s->prec != OD_PREC_FP32) return fail(OD_EINVAL, "the cutoff path runs in FP32 only");
     if (!(r_switch >= 0.0) || !(r_switch < r_cut)) return fail(OD_EINVAL, "need 0 <= r_switch < r_cut");
     const double H = s->sim.H / s->lam, rc = r_cut / s->lam, rs = r_switch / s->lam;
-    const int nslab = (int)std::min<double>(odk::kMaxSlabs, std::max(1.0, std::floor(H / rc)));
+    // slabs of about r_cut / 4 (at most kMaxSlabs), reach = ceil(r_cut / width)
+    const int nslab = (int)std::min<double>(odk::kMaxSlabs, std::max(1.0, std::floor(4.0 * H / rc)));
+    const int reach = (int)std::ceil(rc * nslab / H);
     const int nblk = (int)(s->Npad / 256);
     if (s->cut) free_cutoff(s);
     const size_t P = (size_t)s->Npad;
@@ -783,10 +790,13 @@ od_status od_set_cutoff(od_system* s, double r_switch, double r_cut)
     s->table = (int*)dev_alloc(s, (size_t)nslab * nblk * sizeof(int));
     s->slab_total = (int*)dev_alloc(s, (size_t)nslab * sizeof(int));
     s->slab_start = (int*)dev_alloc(s, (size_t)(nslab + 1) * sizeof(int));
-    if (!s->xs_sorted || !s->idx_sorted || !s->slab || !s->table || !s->slab_total || !s->slab_start) {
+    s->cut_fix = (unsigned long long*)dev_alloc(s, 3 * P * sizeof(unsigned long long));
+    if (!s->xs_sorted || !s->idx_sorted || !s->slab || !s->table || !s->slab_total || !s->slab_start ||
+        !s->cut_fix) {
         free_cutoff(s);
         return fail(OD_ENOMEM, "device allocation of the slab sort failed");
     }
+    HIPCHK(hipMemset(s->cut_fix, 0, 3 * P * sizeof(unsigned long long)));
     // padding slots of the sorted copy sit far away and are never overwritten
     const size_t npad = P - (size_t)s->N;
     if (npad) {
@@ -798,6 +808,7 @@ od_status od_set_cutoff(od_system* s, double r_switch, double r_cut)
     }
     s->ca.nslab = nslab;
     s->ca.nblk = nblk;
+    s->ca.reach = std::max(reach, 1);
     s->ca.z0 = (float)(-0.5 * H);
     s->ca.inv_w = (float)(nslab / H);
     s->ca.rsw = (float)rs;
@@ -820,11 +831,13 @@ od_status od_get_cutoff_info(od_system* s, int32_t* nslab, int64_t* pairs_evalua
         auto slab_at = [&](int64_t p) {
             return (int)(std::upper_bound(start.begin(), start.end(), (int)p) - start.begin()) - 1;
         };
+        // tile I meets tiles I .. J1 - 1; off-diagonal tile pairs count both ways
         int64_t total = 0;
         for (int64_t i0 = 0; i0 < s->N; i0 += 256) {
-            const int lo = slab_at(i0), hi = slab_at(std::min<int64_t>(i0 + 256, s->N) - 1);
-            const int64_t jb = start[std::max(lo - 1, 0)], je = start[std::min(hi + 2, ns)];
-            total += 256 * ((je - jb + kPairTile - 1) / kPairTile) * kPairTile;
+            const int hi = slab_at(std::min<int64_t>(i0 + 256, s->N) - 1);
+            const int64_t je = start[std::min(hi + s->ca.reach + 1, ns)];
+            const int64_t tiles = (je + 255) / 256 - i0 / 256;
+            total += 256 * 256 * (2 * tiles - 1);
         }
         *pairs_evaluated = total;
     }

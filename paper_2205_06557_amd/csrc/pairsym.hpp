@@ -47,6 +47,11 @@ __device__ __forceinline__ float sym_f(float dx, float dy, float dz)
     return fmaf(ri2, ri, ri2) * e;
 }
 
+// The screened Coulomb pair term as a functor for sym_item.
+struct PlainPair {
+    __device__ __forceinline__ float operator()(float dx, float dy, float dz) const { return sym_f(dx, dy, dz); }
+};
+
 __device__ __forceinline__ float rotate_down(float v)
 {
     // lane l receives the value of lane l + 1 (mod 64): DPP wave_rol:1
@@ -55,14 +60,15 @@ __device__ __forceinline__ float rotate_down(float v)
 }
 
 // One work item of one system (positions X, Y, Z; N ions): target tile row
-// I against source tiles [J0, J1).  Reactions go to fix[c * stride + j],
-// the targets' sums to fix[c * stride + i] (indices local to the system).
-template <int BLOCK>
+// I against source tiles [J0, J1), J0 >= I.  Reactions go to
+// fix[c * stride + j], the targets' sums to fix[c * stride + i] (indices
+// local to the system).  pair(d) is the scalar f of the term f d.
+template <int BLOCK, typename Pair>
 __device__ __forceinline__ void sym_item(const float* __restrict__ X, const float* __restrict__ Y,
                                          const float* __restrict__ Z, int N, int I, int J0, int J1,
                                          unsigned long long* __restrict__ fix, long long stride,
                                          double scale, int* status, float4 (*src)[128],
-                                         float (*jpart)[3][BLOCK])
+                                         float (*jpart)[3][BLOCK], const Pair& pair)
 {
     static_assert(BLOCK == 256, "four waves of 64");
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -84,7 +90,7 @@ __device__ __forceinline__ void sym_item(const float* __restrict__ X, const floa
             for (int k = 0; k < BLOCK; ++k) {
                 const float4 q = src[k >> 6][k & 63];
                 const float dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
-                float f = sym_f(dx, dy, dz);
+                float f = pair(dx, dy, dz);
                 f = (k == (int)threadIdx.x) ? 0.0f : f;
                 ax = fmaf(f, dx, ax);
                 ay = fmaf(f, dy, ay);
@@ -98,7 +104,7 @@ __device__ __forceinline__ void sym_item(const float* __restrict__ X, const floa
                 for (int k = 0; k < 64; ++k) {
                     const float4 q = base[k];                 // source (lane + k) mod 64
                     const float dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
-                    const float f = sym_f(dx, dy, dz);
+                    const float f = pair(dx, dy, dz);
                     ax = fmaf(f, dx, ax);
                     ay = fmaf(f, dy, ay);
                     az = fmaf(f, dz, az);
@@ -143,7 +149,7 @@ void pair_sym_kernel(const float* __restrict__ xs, int Npad, int N, double scale
     __shared__ float jpart[4][3][BLOCK];    // reactions per wave
     const SymItem it = items[blockIdx.x];
     sym_item<BLOCK>(xs, xs + Npad, xs + 2 * Npad, N, it.I, it.J0, it.J1, acc_fix, Npad, scale,
-                    &ctl->status, src, jpart);
+                    &ctl->status, src, jpart, PlainPair{});
 }
 
 // Per ion: total of the pair sums, then the terms of pair_epilogue; clears

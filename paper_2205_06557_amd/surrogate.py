@@ -193,8 +193,9 @@ def steps_to_converge(trace: np.ndarray, q_ref: np.ndarray, block: int, tol: flo
     return None
 
 
-def charge_trace(x5, n_ions: int, steps: int, seed: int, q0, block: int = 200):
-    """Charges of a single chain run, sampled every step (batch of one)."""
+def charge_trace(x5, n_ions: int, steps: int, seed: int, q0, every: int = 10):
+    """Charges of a single chain run, read every `every` steps and held in
+    between (the block means of the warm-start study average over them)."""
     from . import binding as B
     w = chain_workload(x5, n_ions, steps, seed, 0, q0)
     s = B.System(w)
@@ -202,9 +203,7 @@ def charge_trace(x5, n_ions: int, steps: int, seed: int, q0, block: int = 200):
     t0 = time.time()
     for k in range(steps):
         s.step(1)
-        if (k + 1) % block == 0 or k + 1 == steps:
-            pass
-        tr[k] = s.charges()[0] if (k % 10 == 0 or k + 1 == steps) else np.nan
+        tr[k] = s.charges()[0] if (k % every == 0 or k + 1 == steps) else np.nan
     s.sync()
     # fill the unsampled steps by holding the last sample (block means only)
     last = tr[0]

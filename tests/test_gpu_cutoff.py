@@ -40,8 +40,9 @@ def test_shadowed_steps_with_cutoff(B, n_ions, H, r_sw, r_cut):
         say("  after 20 free steps", shadow_step(s, o, w))
         ns, npairs = s.cutoff_info()
         say("  slabs", ns, "pairs evaluated", npairs, "of", n_ions * n_ions)
-        # H / r_cut slabs (one fewer if the ratio rounds below an integer)
-        assert ns in (max(1, int(H // r_cut)), max(1, int(H // r_cut) - 1)) and 0 < npairs
+        # about 4 H / r_cut slabs (one fewer if the ratio rounds below an integer)
+        k = int(4 * H // r_cut)
+        assert ns in (max(1, k), max(1, k - 1)) and 0 < npairs
 
 
 def test_far_cutoff_equals_all_pairs(B):

@@ -136,3 +136,29 @@ def test_batch_symmetric_graph_and_oracle(B):
         m = B.BatchMember(eager, 1)
         o = O.Oracle(ws[1])
         say("batch member, symmetric", shadow_step(m, o, ws[1]))
+
+
+def test_sampled_outputs_chain_2p21(B):
+    """The largest all-pairs configuration: the 8-grain chain at 2^21 ions,
+    sampled accelerations and every grain's Eq. (1) and Eq. (2) forces."""
+    w = W.chain8()
+    assert w.n_ions == 1 << 21
+    say("chain of 8 grains", w.n_ions)
+    with B.System(w) as s:
+        assert s.pair_kernel() == B.PAIR_SYMMETRIC
+        s.step(1)
+        o = O.Oracle(w, init=False)
+        from tests.gpu_util import to_oracle
+        to_oracle(s, o)
+        s.step(1)
+        s.sync()
+        a = s.accelerations().T.astype(np.float64)
+        lam, wpi = o.derived["lam"], o.derived["wpi"]
+        idx = np.sort(np.random.default_rng(21).choice(w.n_ions, size=256, replace=False))
+        l2, p999, pmax = accel_errors(a[idx] * lam * wpi * wpi, o.accel_subset(idx))
+        say("  sampled accel errors", l2, p999, pmax)
+        assert l2 <= 1e-5 and p999 <= 1e-5
+        F, Fo = s.forces(0), o.dust_forces()
+        for d in range(8):
+            for p in (0, 1, 3):
+                assert np.linalg.norm(F[d, p] - Fo[d, p]) <= 1e-5 * np.linalg.norm(Fo[d, p]) + 1e-300, (d, p)
