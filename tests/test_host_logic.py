@@ -77,3 +77,18 @@ def test_sweep_inputs_inside_box_and_seeded():
     assert (X >= S.BOX_LO).all() and (X <= S.BOX_HI).all()
     assert np.array_equal(X, S.sweep_inputs(500, 7))
     assert not np.array_equal(X, S.sweep_inputs(500, 8))
+
+
+def test_pmc_summary_maps_the_symmetric_pair_kernels(tmp_path):
+    f = tmp_path / "f.csv"
+    w = tmp_path / "w.csv"
+    _write_counters(f, [("__amd_rocclr_copyBuffer", "FETCH_SIZE", 131072.0),
+                        ("void odk::pair_sym_kernel<256>(float const*, int, int, double, ...)", "FETCH_SIZE", 4000.0),
+                        ("odk::pair_sym_epilogue(float const*, ...)", "FETCH_SIZE", 30.0)])
+    _write_counters(w, [("__amd_rocclr_copyBuffer", "WRITE_SIZE", 262144.0),
+                        ("void odk::pair_sym_kernel<256>(float const*, int, int, double, ...)", "WRITE_SIZE", 9000.0),
+                        ("odk::pair_sym_epilogue(float const*, ...)", "WRITE_SIZE", 20.0)])
+    s = P.summarise(str(f), str(w), 1 << 20)
+    assert s["kernels"]["pair"]["fetch_bytes"] == pytest.approx(4000.0 * 1024 / 0.5)
+    assert s["kernels"]["pair"]["write_bytes"] == pytest.approx(9000.0 * 1024)
+    assert s["kernels"]["pair_epilogue"]["traffic_bytes"] == pytest.approx((30.0 / 0.5 + 20.0) * 1024)
