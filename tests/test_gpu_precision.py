@@ -86,6 +86,9 @@ def test_precision_report(B):
         for k in range(steps):
             s32.step(1)
             s64.step(1)
+            if (k + 1) % 20 == 0:
+                s64.sync()
+                say(f"  free-running steps {k + 1}/{steps}")
             for name, s in (("fp32", s32), ("fp64", s64)):
                 if k % 5 == 0:
                     qn, _ = s.charges()
