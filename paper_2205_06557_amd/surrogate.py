@@ -10,7 +10,7 @@ run on inputs drawn uniformly in the input box.  Uses:
 * warm start: the predicted charges start a full simulation near its
   self-consistent state;
 * fast evaluator: charges and forces without simulating, with the full
-  method as the fallback outside the input box and as the judge of error.
+  method as the fallback outside the input box and as the reference for its error.
 
 Targets are made dimensionless before training: charge by
 4 pi eps0 a k_B T_e / e (grain potential in units of k_B T_e / e) and force
@@ -244,7 +244,7 @@ def _load(data: str, tag: str, with_meta: bool = False):
 
 
 def evaluate(data: str, out: str, epochs: int, eval_ions: int, eval_steps: int, seed: int = 11):
-    """Trains on DATA/train_*.npz, judges against DATA/testa_*.npz and
+    """Trains on DATA/train_*.npz, compares with DATA/testa_*.npz and
     DATA/testb_*.npz (the same held-out inputs, two random streams), and runs
     the warm-start study; writes OUT/surrogate_result.json."""
     os.makedirs(out, exist_ok=True)
@@ -267,19 +267,19 @@ def evaluate(data: str, out: str, epochs: int, eval_ions: int, eval_steps: int, 
     t2 = time.time()
     P, inside = sur.predict_targets(Xt)
     res["predict_s_per_point"] = (time.time() - t2) / len(Xt)
-    judge = 0.5 * (Ta + Tb)
-    q_err = np.abs(P[:, :8] / judge[:, :8] - 1.0)
+    ref = 0.5 * (Ta + Tb)
+    q_err = np.abs(P[:, :8] / ref[:, :8] - 1.0)
     q_noise = np.abs(Ta[:, :8] / Tb[:, :8] - 1.0) / math.sqrt(2)
-    fscale = np.abs(judge[:, 8:]).mean(axis=1, keepdims=True)
-    f_err = np.abs(P[:, 8:] - judge[:, 8:]) / fscale
+    fscale = np.abs(ref[:, 8:]).mean(axis=1, keepdims=True)
+    f_err = np.abs(P[:, 8:] - ref[:, 8:]) / fscale
     f_noise = np.abs(Ta[:, 8:] - Tb[:, 8:]) / fscale / math.sqrt(2)
 
     def st(a):
         return {"median": float(np.median(a)), "p90": float(np.percentile(a, 90)), "mean": float(a.mean())}
     res["charge_rel_err"] = st(q_err)
-    res["charge_noise_of_judge"] = st(q_noise)
+    res["charge_noise_of_reference"] = st(q_noise)
     res["force_rel_err_vs_mean_abs"] = st(f_err)
-    res["force_noise_of_judge"] = st(f_noise)
+    res["force_noise_of_reference"] = st(f_noise)
     res["inside_box"] = int(inside.sum())
     # warm start vs cold start on one chain at a larger N
     x5 = np.array([1.0, 5.0, 0.4, 0.1, 33.3])
