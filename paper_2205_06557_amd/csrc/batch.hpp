@@ -83,7 +83,7 @@ void pair_batch_kernel(const float* __restrict__ xs,
 // pairsym.hpp): item = (system, target tile row, source tile run); int64
 // fixed-point totals in fix (planes `plane` apart, system at its offset).
 struct SymBatchItem {
-    int sys, I, J0, J1;
+    int sys, I, J0, J1, rows, pad_[3];
 };
 
 template <int BLOCK, int TJ>
@@ -99,9 +99,13 @@ void pair_sym_batch_kernel(const float* __restrict__ xs, long long plane, const 
     const int s = uniform_int(it.sys);
     const long long off = sys[s].off;
     const float* X = xs + off;
-    sym_item<BLOCK>(X, X + plane, X + 2 * plane, sys[s].pa.N, uniform_int(it.I), uniform_int(it.J0),
-                    uniform_int(it.J1), fix + off, plane, sys[s].pa.sym_scale, &ctls[s].status, src,
-                    jpart, PlainPair{});
+    const int I = uniform_int(it.I), J0 = uniform_int(it.J0), J1 = uniform_int(it.J1);
+    if (uniform_int(it.rows) == 2)
+        sym_item2<BLOCK>(X, X + plane, X + 2 * plane, sys[s].pa.N, I, J0, J1, fix + off, plane,
+                         sys[s].pa.sym_scale, &ctls[s].status, src, jpart, PlainPair{});
+    else
+        sym_item<BLOCK>(X, X + plane, X + 2 * plane, sys[s].pa.N, I, J0, J1, fix + off, plane,
+                        sys[s].pa.sym_scale, &ctls[s].status, src, jpart, PlainPair{});
 }
 
 // Per ion of every system (block b belongs to system blk_sys[b]): converts

@@ -179,17 +179,19 @@ void free_sym(od_system* s)
     s->sym = false;
 }
 
-// Work items of the symmetric sum of one system of T tiles: runs of at most
-// C source tiles J >= I of each target tile row I, C chosen for about
-// kSymItemsTarget items.  The split depends on T only, so a system's sums are
-// grouped the same way alone and in a batch.
+// Work items of the symmetric sum of one system of T tiles: target tile rows
+// in pairs (2R, 2R + 1), each pair with runs of at most C source tiles from
+// J = 2R on (an odd last row alone), C chosen for about kSymItemsTarget
+// items.  The split depends on T only, so a system's sums are grouped the
+// same way alone and in a batch.
 std::vector<odk::SymItem> sym_items_of(int T)
 {
     const double pairs = 0.5 * (double)T * (T + 1);
-    const int C = (int)std::max(1.0, std::ceil(pairs / kSymItemsTarget));
+    const int C = (int)std::max(2.0, std::ceil(pairs / (2.0 * kSymItemsTarget)));
     std::vector<odk::SymItem> v;
-    for (int I = 0; I < T; ++I)
-        for (int J0 = I; J0 < T; J0 += C) v.push_back({I, J0, std::min(J0 + C, T), 0});
+    for (int I = 0; I + 1 < T; I += 2)
+        for (int J0 = I; J0 < T; J0 += C) v.push_back({I, J0, std::min(J0 + C, T), 2});
+    if (T % 2) v.push_back({T - 1, T - 1, T, 1});
     return v;
 }
 

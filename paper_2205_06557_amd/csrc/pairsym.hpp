@@ -31,8 +31,10 @@ namespace odk {
 // nearest neighbours, ~ n^(2/3)) while the int64 range keeps a margin of
 // about 1e13 for close pairs.
 
+// rows == 1: target tile row I against source tiles [J0, J1) (sym_item);
+// rows == 2: target tile rows I and I + 1 together (sym_item2).
 struct SymItem {
-    int I, J0, J1, pad_;
+    int I, J0, J1, rows;
 };
 
 // One pair term (1 + r) e^-r / r^3 for the difference d.
@@ -139,6 +141,89 @@ __device__ __forceinline__ void sym_item(const float* __restrict__ X, const floa
     }
 }
 
+// Two target tile rows Ia = I and Ib = I + 1 against source tiles [J0, J1):
+// each lane holds one target of each row, so one source (and one rotation
+// of its reaction accumulator) serves two pairs.  The 2 x 2 block of the rows'
+// own tiles is summed by sym_item first when J0 == I; the joint loop then
+// starts at I + 2, where both rows are below the sources.
+template <int BLOCK, typename Pair>
+__device__ __forceinline__ void sym_item2(const float* __restrict__ X, const float* __restrict__ Y,
+                                          const float* __restrict__ Z, int N, int I, int J0, int J1,
+                                          unsigned long long* __restrict__ fix, long long stride,
+                                          double scale, int* status, float4 (*src)[128],
+                                          float (*jpart)[3][BLOCK], const Pair& pair)
+{
+    if (J0 == I) {
+        sym_item<BLOCK>(X, Y, Z, N, I, I, I + 2, fix, stride, scale, status, src, jpart, pair);
+        sym_item<BLOCK>(X, Y, Z, N, I + 1, I + 1, I + 2, fix, stride, scale, status, src, jpart, pair);
+        J0 = I + 2;
+    }
+    if (J0 >= J1) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int ia = I * BLOCK + threadIdx.x, ib = ia + BLOCK;
+    const float xa = X[ia], ya = Y[ia], za = Z[ia];
+    const float xb = X[ib], yb = Y[ib], zb = Z[ib];
+    double sxa = 0.0, sya = 0.0, sza = 0.0, sxb = 0.0, syb = 0.0, szb = 0.0;
+    for (int J = J0; J < J1; ++J) {
+        const int j0 = J * BLOCK;
+        __syncthreads();
+        {
+            const int st = threadIdx.x >> 6, l = threadIdx.x & 63;
+            const float4 q = make_float4(X[j0 + threadIdx.x], Y[j0 + threadIdx.x], Z[j0 + threadIdx.x], 0.0f);
+            src[st][l] = q;
+            src[st][l + 64] = q;
+        }
+        __syncthreads();
+        float axa = 0.0f, aya = 0.0f, aza = 0.0f, axb = 0.0f, ayb = 0.0f, azb = 0.0f;
+        for (int st = 0; st < 4; ++st) {
+            float jx = 0.0f, jy = 0.0f, jz = 0.0f;
+            const float4* base = &src[st][lane];
+#pragma unroll 8
+            for (int k = 0; k < 64; ++k) {
+                const float4 q = base[k];                     // source (lane + k) mod 64
+                const float dxa = xa - q.x, dya = ya - q.y, dza = za - q.z;
+                const float dxb = xb - q.x, dyb = yb - q.y, dzb = zb - q.z;
+                const float fa = pair(dxa, dya, dza);
+                const float fb = pair(dxb, dyb, dzb);
+                axa = fmaf(fa, dxa, axa);
+                aya = fmaf(fa, dya, aya);
+                aza = fmaf(fa, dza, aza);
+                axb = fmaf(fb, dxb, axb);
+                ayb = fmaf(fb, dyb, ayb);
+                azb = fmaf(fb, dzb, azb);
+                jx = fmaf(-fb, dxb, fmaf(-fa, dxa, rotate_down(jx)));
+                jy = fmaf(-fb, dyb, fmaf(-fa, dya, rotate_down(jy)));
+                jz = fmaf(-fb, dzb, fmaf(-fa, dza, rotate_down(jz)));
+            }
+            const int sid = st * 64 + ((lane + 63) & 63);
+            jpart[wv][0][sid] = jx;
+            jpart[wv][1][sid] = jy;
+            jpart[wv][2][sid] = jz;
+        }
+        __syncthreads();
+        const int j = j0 + threadIdx.x;
+        if (j < N) {
+            for (int c = 0; c < 3; ++c) {
+                const float v = ((jpart[0][c][threadIdx.x] + jpart[1][c][threadIdx.x]) +
+                                 jpart[2][c][threadIdx.x]) + jpart[3][c][threadIdx.x];
+                atomicAdd(&fix[c * stride + j], to_fixed((double)v, scale, status));
+            }
+        }
+        sxa += (double)axa; sya += (double)aya; sza += (double)aza;
+        sxb += (double)axb; syb += (double)ayb; szb += (double)azb;
+    }
+    if (ia < N) {
+        atomicAdd(&fix[ia], to_fixed(sxa, scale, status));
+        atomicAdd(&fix[stride + ia], to_fixed(sya, scale, status));
+        atomicAdd(&fix[2 * stride + ia], to_fixed(sza, scale, status));
+    }
+    if (ib < N) {
+        atomicAdd(&fix[ib], to_fixed(sxb, scale, status));
+        atomicAdd(&fix[stride + ib], to_fixed(syb, scale, status));
+        atomicAdd(&fix[2 * stride + ib], to_fixed(szb, scale, status));
+    }
+}
+
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8, 8)))
 void pair_sym_kernel(const float* __restrict__ xs, int Npad, int N, double scale,
@@ -148,8 +233,12 @@ void pair_sym_kernel(const float* __restrict__ xs, int Npad, int N, double scale
     __shared__ float4 src[4][128];          // sub-tiles of 64 sources, each stored twice
     __shared__ float jpart[4][3][BLOCK];    // reactions per wave
     const SymItem it = items[blockIdx.x];
-    sym_item<BLOCK>(xs, xs + Npad, xs + 2 * Npad, N, it.I, it.J0, it.J1, acc_fix, Npad, scale,
-                    &ctl->status, src, jpart, PlainPair{});
+    if (it.rows == 2)
+        sym_item2<BLOCK>(xs, xs + Npad, xs + 2 * Npad, N, it.I, it.J0, it.J1, acc_fix, Npad, scale,
+                         &ctl->status, src, jpart, PlainPair{});
+    else
+        sym_item<BLOCK>(xs, xs + Npad, xs + 2 * Npad, N, it.I, it.J0, it.J1, acc_fix, Npad, scale,
+                        &ctl->status, src, jpart, PlainPair{});
 }
 
 // Per ion: total of the pair sums, then the terms of pair_epilogue; clears

@@ -162,3 +162,20 @@ def test_sampled_outputs_chain_2p21(B):
         for d in range(8):
             for p in (0, 1, 3):
                 assert np.linalg.norm(F[d, p] - Fo[d, p]) <= 1e-5 * np.linalg.norm(Fo[d, p]) + 1e-300, (d, p)
+
+
+def test_fixed_point_overflow_is_reported(B):
+    """Two ions 1e-12 r_De apart make a pair sum far beyond the accumulators'
+    range: the step must end with OD_ENUMERIC (the kernel clamps and flags),
+    not with silently wrapped sums."""
+    w = W.single_grain_small().with_(n_ions=600, dust=[])
+    with B.System(w) as s:
+        x, v, q, st = s.get_state()
+        x = x.copy()
+        x[:, 0] = (0.0, 0.0, 0.5)
+        x[:, 1] = (1e-12, 0.0, 0.5)
+        s.set_state(x, None, None, st)
+        s.step(1)
+        with pytest.raises(B.OdError) as e:
+            s.sync()
+        assert e.value.status == B.OD_ENUMERIC
