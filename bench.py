@@ -146,6 +146,51 @@ def cutoff_bench(args):
     print(json.dumps(res), flush=True)
 
 
+def crossover_bench(args):
+    """Pair-phase time per launch of the one-sided and the symmetric all-pairs
+    kernels on the single-grain workload at 2^12 .. 2^20 ions (HIP events on
+    the launch stream, K steps after the warm-up)."""
+    import torch
+    from paper_2205_06557_amd import binding as B
+    from paper_2205_06557_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    rows = []
+    for lg in range(12, 21, 2):
+        w = W.single_grain_small().with_(n_ions=1 << lg)
+        row = {"n_ions": w.n_ions}
+        for name, kind in (("one_sided", B.PAIR_ONE_SIDED), ("symmetric", B.PAIR_SYMMETRIC)):
+            s = B.System(w)
+            s.set_pair_kernel(kind)
+            s.step(args.warmup)
+            s.sync()
+            s.set_timing(True)
+            s.step(args.steps)
+            s.sync()
+            kt = s.kernel_times()
+            s.close()
+            row[name + "_pair_ms"] = kt["pair"][0] / max(kt["pair"][1], 1)
+        row["speedup"] = row["one_sided_pair_ms"] / row["symmetric_pair_ms"]
+        rows.append(row)
+        print(f"[bench] crossover N=2^{lg}: one-sided {row['one_sided_pair_ms']:.4f} ms, "
+              f"symmetric {row['symmetric_pair_ms']:.4f} ms", file=sys.stderr, flush=True)
+    big = rows[-1]
+    achieved = FLOP_PER_PAIR * big["n_ions"] * (big["n_ions"] - 1) / (big["symmetric_pair_ms"] * 1e-3)
+    res = {
+        "metric": "pair-phase time per launch, one-sided vs symmetric all-pairs kernel",
+        "value": big["symmetric_pair_ms"], "unit": "ms", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "one 5 um grain, R = 3 r_De, H = 6 r_De, Mach 1, nu = 0.1 omega_pi",
+                   "n_ions": big["n_ions"]},
+        "series": rows,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
+                     "kernel": "pair_sym_kernel at the largest N", "flop_per_pair": FLOP_PER_PAIR},
+    }
+    print(json.dumps(res), flush=True)
+
+
 def batch_bench(args):
     """Batched sweep: 64 single-grain systems, log2 N ~ U(14, 17), Mach, radius
     and collision frequency drawn per system; one launch per phase for all
@@ -233,7 +278,12 @@ def main():
                     help="the constant-concentration series with the ion-ion cutoff")
     ap.add_argument("--batch", action="store_true",
                     help="the batched 64-system sweep instead of the 2^20-ion two-grain workload")
+    ap.add_argument("--crossover", action="store_true",
+                    help="pair-phase times of the one-sided and symmetric kernels, 2^12 .. 2^20 ions")
     args = ap.parse_args()
+    if args.crossover and args.gpus == 1:
+        crossover_bench(args)
+        return
     if args.batch and args.gpus == 1:
         sys.path.insert(0, ROOT)
         batch_bench(args)

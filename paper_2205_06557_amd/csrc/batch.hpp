@@ -87,7 +87,7 @@ struct SymBatchItem {
 };
 
 template <int BLOCK, int TJ>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8, 8)))
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(kSymWaves, 8)))
 void pair_sym_batch_kernel(const float* __restrict__ xs, long long plane, const SysDesc* sys,
                            Ctl* __restrict__ ctls, const SymBatchItem* __restrict__ items,
                            unsigned long long* __restrict__ fix)
@@ -100,12 +100,8 @@ void pair_sym_batch_kernel(const float* __restrict__ xs, long long plane, const 
     const long long off = sys[s].off;
     const float* X = xs + off;
     const int I = uniform_int(it.I), J0 = uniform_int(it.J0), J1 = uniform_int(it.J1);
-    if (uniform_int(it.rows) == 2)
-        sym_item2<BLOCK>(X, X + plane, X + 2 * plane, sys[s].pa.N, I, J0, J1, fix + off, plane,
-                         sys[s].pa.sym_scale, &ctls[s].status, src, jpart, PlainPair{});
-    else
-        sym_item<BLOCK>(X, X + plane, X + 2 * plane, sys[s].pa.N, I, J0, J1, fix + off, plane,
-                        sys[s].pa.sym_scale, &ctls[s].status, src, jpart, PlainPair{});
+    sym_dispatch<BLOCK>(X, X + plane, X + 2 * plane, sys[s].pa.N, uniform_int(it.rows), I, J0, J1, fix + off,
+                        plane, sys[s].pa.sym_scale, &ctls[s].status, src, jpart, PlainPair{});
 }
 
 // Per ion of every system (block b belongs to system blk_sys[b]): converts

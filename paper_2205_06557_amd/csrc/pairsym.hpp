@@ -31,8 +31,16 @@ namespace odk {
 // nearest neighbours, ~ n^(2/3)) while the int64 range keeps a margin of
 // about 1e13 for close pairs.
 
+// Target tile rows that share one pass over the sources (sym_rows), and the
+// occupancy the symmetric kernels are compiled for (75 VGPRs at three rows).
+// Three rows at six waves per SIMD, with the step written as differences,
+// pair terms, then sums, timed fastest among 2 to 4 rows, four statement
+// orders, 16 or 32 unrolled steps and 5 to 8 waves per SIMD on gfx950.
+constexpr int kSymRows = 3;
+constexpr int kSymWaves = 6;
+
 // rows == 1: target tile row I against source tiles [J0, J1) (sym_item);
-// rows == 2: target tile rows I and I + 1 together (sym_item2).
+// rows == kSymRows: target tile rows I .. I + kSymRows - 1 together (sym_rows).
 struct SymItem {
     int I, J0, J1, rows;
 };
@@ -141,29 +149,35 @@ __device__ __forceinline__ void sym_item(const float* __restrict__ X, const floa
     }
 }
 
-// Two target tile rows Ia = I and Ib = I + 1 against source tiles [J0, J1):
-// each lane holds one target of each row, so one source (and one rotation
-// of its reaction accumulator) serves two pairs.  The 2 x 2 block of the rows'
-// own tiles is summed by sym_item first when J0 == I; the joint loop then
-// starts at I + 2, where both rows are below the sources.
-template <int BLOCK, typename Pair>
-__device__ __forceinline__ void sym_item2(const float* __restrict__ X, const float* __restrict__ Y,
-                                          const float* __restrict__ Z, int N, int I, int J0, int J1,
-                                          unsigned long long* __restrict__ fix, long long stride,
-                                          double scale, int* status, float4 (*src)[128],
-                                          float (*jpart)[3][BLOCK], const Pair& pair)
+// R target tile rows I .. I + R - 1 against source tiles [J0, J1): each lane
+// holds one target of every row, so one source (and one rotation of its
+// reaction accumulator) serves R pairs.  When J0 == I the R x R block of the
+// rows' own tiles is summed first by sym_item; the joint loop then starts at
+// I + R, where every row is below the sources.
+template <int BLOCK, int R, typename Pair>
+__device__ __forceinline__ void sym_rows(const float* __restrict__ X, const float* __restrict__ Y,
+                                         const float* __restrict__ Z, int N, int I, int J0, int J1,
+                                         unsigned long long* __restrict__ fix, long long stride,
+                                         double scale, int* status, float4 (*src)[128],
+                                         float (*jpart)[3][BLOCK], const Pair& pair)
 {
     if (J0 == I) {
-        sym_item<BLOCK>(X, Y, Z, N, I, I, I + 2, fix, stride, scale, status, src, jpart, pair);
-        sym_item<BLOCK>(X, Y, Z, N, I + 1, I + 1, I + 2, fix, stride, scale, status, src, jpart, pair);
-        J0 = I + 2;
+        for (int r = 0; r < R; ++r)
+            sym_item<BLOCK>(X, Y, Z, N, I + r, I + r, I + R, fix, stride, scale, status, src, jpart, pair);
+        J0 = I + R;
     }
     if (J0 >= J1) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int ia = I * BLOCK + threadIdx.x, ib = ia + BLOCK;
-    const float xa = X[ia], ya = Y[ia], za = Z[ia];
-    const float xb = X[ib], yb = Y[ib], zb = Z[ib];
-    double sxa = 0.0, sya = 0.0, sza = 0.0, sxb = 0.0, syb = 0.0, szb = 0.0;
+    float xt[R], yt[R], zt[R];
+    double sx[R], sy[R], sz[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = (I + r) * BLOCK + threadIdx.x;
+        xt[r] = X[i];
+        yt[r] = Y[i];
+        zt[r] = Z[i];
+        sx[r] = sy[r] = sz[r] = 0.0;
+    }
     for (int J = J0; J < J1; ++J) {
         const int j0 = J * BLOCK;
         __syncthreads();
@@ -174,26 +188,33 @@ __device__ __forceinline__ void sym_item2(const float* __restrict__ X, const flo
             src[st][l + 64] = q;
         }
         __syncthreads();
-        float axa = 0.0f, aya = 0.0f, aza = 0.0f, axb = 0.0f, ayb = 0.0f, azb = 0.0f;
+        float ax[R], ay[R], az[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) ax[r] = ay[r] = az[r] = 0.0f;
         for (int st = 0; st < 4; ++st) {
             float jx = 0.0f, jy = 0.0f, jz = 0.0f;
             const float4* base = &src[st][lane];
-#pragma unroll 8
+#pragma unroll 32
             for (int k = 0; k < 64; ++k) {
                 const float4 q = base[k];                     // source (lane + k) mod 64
-                const float dxa = xa - q.x, dya = ya - q.y, dza = za - q.z;
-                const float dxb = xb - q.x, dyb = yb - q.y, dzb = zb - q.z;
-                const float fa = pair(dxa, dya, dza);
-                const float fb = pair(dxb, dyb, dzb);
-                axa = fmaf(fa, dxa, axa);
-                aya = fmaf(fa, dya, aya);
-                aza = fmaf(fa, dza, aza);
-                axb = fmaf(fb, dxb, axb);
-                ayb = fmaf(fb, dyb, ayb);
-                azb = fmaf(fb, dzb, azb);
-                jx = fmaf(-fb, dxb, fmaf(-fa, dxa, rotate_down(jx)));
-                jy = fmaf(-fb, dyb, fmaf(-fa, dya, rotate_down(jy)));
-                jz = fmaf(-fb, dzb, fmaf(-fa, dza, rotate_down(jz)));
+                float dx[R], dy[R], dz[R], f[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    dx[r] = xt[r] - q.x;
+                    dy[r] = yt[r] - q.y;
+                    dz[r] = zt[r] - q.z;
+                }
+#pragma unroll
+                for (int r = 0; r < R; ++r) f[r] = pair(dx[r], dy[r], dz[r]);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    ax[r] = fmaf(f[r], dx[r], ax[r]);
+                    ay[r] = fmaf(f[r], dy[r], ay[r]);
+                    az[r] = fmaf(f[r], dz[r], az[r]);
+                    jx = fmaf(-f[r], dx[r], r == 0 ? rotate_down(jx) : jx);
+                    jy = fmaf(-f[r], dy[r], r == 0 ? rotate_down(jy) : jy);
+                    jz = fmaf(-f[r], dz[r], r == 0 ? rotate_down(jz) : jz);
+                }
             }
             const int sid = st * 64 + ((lane + 63) & 63);
             jpart[wv][0][sid] = jx;
@@ -209,23 +230,40 @@ __device__ __forceinline__ void sym_item2(const float* __restrict__ X, const flo
                 atomicAdd(&fix[c * stride + j], to_fixed((double)v, scale, status));
             }
         }
-        sxa += (double)axa; sya += (double)aya; sza += (double)aza;
-        sxb += (double)axb; syb += (double)ayb; szb += (double)azb;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            sx[r] += (double)ax[r];
+            sy[r] += (double)ay[r];
+            sz[r] += (double)az[r];
+        }
     }
-    if (ia < N) {
-        atomicAdd(&fix[ia], to_fixed(sxa, scale, status));
-        atomicAdd(&fix[stride + ia], to_fixed(sya, scale, status));
-        atomicAdd(&fix[2 * stride + ia], to_fixed(sza, scale, status));
-    }
-    if (ib < N) {
-        atomicAdd(&fix[ib], to_fixed(sxb, scale, status));
-        atomicAdd(&fix[stride + ib], to_fixed(syb, scale, status));
-        atomicAdd(&fix[2 * stride + ib], to_fixed(szb, scale, status));
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = (I + r) * BLOCK + threadIdx.x;
+        if (i < N) {
+            atomicAdd(&fix[i], to_fixed(sx[r], scale, status));
+            atomicAdd(&fix[stride + i], to_fixed(sy[r], scale, status));
+            atomicAdd(&fix[2 * stride + i], to_fixed(sz[r], scale, status));
+        }
     }
 }
 
+// One work item: rows == 1 is sym_item, rows == kSymRows is sym_rows.
+template <int BLOCK, typename Pair>
+__device__ __forceinline__ void sym_dispatch(const float* __restrict__ X, const float* __restrict__ Y,
+                                             const float* __restrict__ Z, int N, int rows, int I, int J0,
+                                             int J1, unsigned long long* __restrict__ fix, long long stride,
+                                             double scale, int* status, float4 (*src)[128],
+                                             float (*jpart)[3][BLOCK], const Pair& pair)
+{
+    if (rows == kSymRows)
+        sym_rows<BLOCK, kSymRows>(X, Y, Z, N, I, J0, J1, fix, stride, scale, status, src, jpart, pair);
+    else
+        sym_item<BLOCK>(X, Y, Z, N, I, J0, J1, fix, stride, scale, status, src, jpart, pair);
+}
+
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8, 8)))
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(kSymWaves, 8)))
 void pair_sym_kernel(const float* __restrict__ xs, int Npad, int N, double scale,
                      const SymItem* __restrict__ items, unsigned long long* __restrict__ acc_fix,
                      Ctl* __restrict__ ctl)
@@ -233,11 +271,7 @@ void pair_sym_kernel(const float* __restrict__ xs, int Npad, int N, double scale
     __shared__ float4 src[4][128];          // sub-tiles of 64 sources, each stored twice
     __shared__ float jpart[4][3][BLOCK];    // reactions per wave
     const SymItem it = items[blockIdx.x];
-    if (it.rows == 2)
-        sym_item2<BLOCK>(xs, xs + Npad, xs + 2 * Npad, N, it.I, it.J0, it.J1, acc_fix, Npad, scale,
-                         &ctl->status, src, jpart, PlainPair{});
-    else
-        sym_item<BLOCK>(xs, xs + Npad, xs + 2 * Npad, N, it.I, it.J0, it.J1, acc_fix, Npad, scale,
+    sym_dispatch<BLOCK>(xs, xs + Npad, xs + 2 * Npad, N, it.rows, it.I, it.J0, it.J1, acc_fix, Npad, scale,
                         &ctl->status, src, jpart, PlainPair{});
 }
 

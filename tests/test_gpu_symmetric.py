@@ -97,7 +97,8 @@ def _batch_systems():
     return [base.with_(n_ions=1500, system_id=0),
             base.with_(n_ions=4099, system_id=1, mach=0.6, nu_in=0.2 * base.wpi),
             base.with_(n_ions=700, system_id=2, flags=W.FLAG_NO_ION_ION),
-            W.two_grain_wake().with_(n_ions=2600, system_id=3, seed=3)]
+            W.two_grain_wake().with_(n_ions=2600, system_id=3, seed=3),
+            base.with_(n_ions=(1 << 16) + 600, system_id=4, seed=5)]    # grouped target rows
 
 
 def test_batch_symmetric_equals_single(B):
@@ -136,6 +137,31 @@ def test_batch_symmetric_graph_and_oracle(B):
         m = B.BatchMember(eager, 1)
         o = O.Oracle(ws[1])
         say("batch member, symmetric", shadow_step(m, o, ws[1]))
+
+
+@pytest.mark.parametrize("n_ions", [(1 << 16) + 600, (1 << 16) + 412])
+def test_grouped_rows_sampled_parity(B, n_ions):
+    """Systems large enough for items of three target rows (259 tiles: one
+    row left over; 258 tiles: none), both with a ragged last tile: sampled
+    accelerations against the oracle, the last 600 ions included."""
+    w = W.single_grain_small().with_(n_ions=n_ions)
+    say("grouped rows, N", n_ions)
+    with B.System(w) as s:
+        assert s.pair_kernel() == B.PAIR_SYMMETRIC
+        s.step(1)
+        o = O.Oracle(w, init=False)
+        from tests.gpu_util import to_oracle
+        to_oracle(s, o)
+        s.step(1)
+        s.sync()
+        a = s.accelerations().T.astype(np.float64)
+        lam, wpi = o.derived["lam"], o.derived["wpi"]
+        rng = np.random.default_rng(n_ions)
+        idx = np.unique(np.concatenate([rng.choice(n_ions - 600, size=200, replace=False),
+                                        np.arange(n_ions - 600, n_ions, 5)]))
+        l2, p999, pmax = accel_errors(a[idx] * lam * wpi * wpi, o.accel_subset(idx))
+        say("  sampled accel errors", l2, p999, pmax)
+        assert l2 <= 1e-5 and p999 <= 1e-5
 
 
 def test_sampled_outputs_chain_2p21(B):
