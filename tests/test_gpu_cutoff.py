@@ -58,8 +58,12 @@ def test_far_cutoff_equals_all_pairs(B):
         assert l2 < 2e-6 and p999 < 5e-6
 
 
-def test_sampled_outputs_long_domain(B):
-    w = W.long_domain(1 << 20)
+@pytest.mark.parametrize("n_ions", [1 << 20, (1 << 21) + 600])
+def test_sampled_outputs_long_domain(B, n_ions):
+    """Sampled accelerations and grain forces against the oracle in the long
+    domain, at 2^20 ions and at 2^21 + 600 (192 slabs, 8195 sorted tiles, a
+    ragged last tile; the last 600 ions are in the sample)."""
+    w = W.long_domain(n_ions)
     say("long domain", w.n_ions, "H/lambda", w.H / LAM)
     with B.System(w) as s:
         s.set_cutoff(W.CUTOFF_SWITCH, W.CUTOFF_RADIUS)
@@ -71,7 +75,8 @@ def test_sampled_outputs_long_domain(B):
         s.sync()
         a = s.accelerations().T.astype(np.float64)
         lam, wpi = o.derived["lam"], o.derived["wpi"]
-        idx = np.sort(np.random.default_rng(3).choice(w.n_ions, size=384, replace=False))
+        idx = np.unique(np.concatenate([np.random.default_rng(3).choice(w.n_ions, size=384, replace=False),
+                                        np.arange(w.n_ions - 600, w.n_ions, 8)]))
         ref = o.accel_subset(idx)
         l2, p999, pmax = accel_errors(a[idx] * lam * wpi * wpi, ref)
         say("  sampled accel errors", l2, p999, pmax)
