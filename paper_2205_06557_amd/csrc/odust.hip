@@ -41,7 +41,7 @@ constexpr int kPad = 256;
 constexpr int kReinjGrid = 2 * odk::kSlots;   // a multiple of the lost-list segments
 constexpr int kMaxSplitSingle = 4;             // source splits of one system's pair sum
 constexpr int kSymMinTiles = 1;               // all-pairs sum with each pair once: at every size
-constexpr double kSymItemsTarget = 16384.0;    // work items of the symmetric sum
+constexpr double kSymItemsTarget = 65536.0;    // work items of the symmetric sum
 constexpr double kSymMinGroupedItems = 2048.0; // fewer grouped items: one target row per item
 constexpr int kConfNr = 32, kConfNz = 32;      // intervals of the confinement grid along r, z
 constexpr int kConfNodes = (kConfNr + 1) * (kConfNz + 1);

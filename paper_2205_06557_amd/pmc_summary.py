@@ -6,8 +6,8 @@ FETCH_SIZE, one WRITE_SIZE, in KiB per dispatch) are combined.  Each counter is
 divided by what it reads for the calibration copy of 256 MiB (a plain
 device-to-device copy whose source was first evicted from the Infinity
 Cache), which converts counter units into bytes moved.  The result is stamped
-with a hash of the kernel sources: bench.py reports the traffic only while the
-kernels are unchanged.
+with a hash of the kernel sources and of the host code that splits their work:
+bench.py reports the traffic only while both are unchanged.
 
     python -m paper_2205_06557_amd.pmc_summary --fetch F.csv --write W.csv \\
         --n-ions 1048576 --json profiles/step_kernels_traffic.json --md profiles/step_kernels_traffic.md
@@ -22,7 +22,8 @@ import json
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ("csrc/kernels.hpp", "csrc/device_common.hpp", "csrc/cutoff.hpp", "csrc/pairsym.hpp")
+KERNEL_SOURCES = ("csrc/kernels.hpp", "csrc/device_common.hpp", "csrc/cutoff.hpp", "csrc/pairsym.hpp",
+                  "csrc/odust.hip")
 CALIB_BYTES = 1 << 28
 KERNELS = {"pair_forces_f32": "pair", "pair_sym_kernel": "pair", "pair_sym_epilogue": "pair_epilogue",
            "push_kernel<float>": "push", "reinject_kernel<float>": "reinject", "finalize_kernel": "finalize"}
