@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 
 FLOP_PER_PAIR = 23            # algorithmic FP32 flop per ordered pair
 PEAK_FP32 = 157.3e12          # MI355X published FP32 vector peak (counts packed FP32)
+PEAK_FP64 = 78.6e12           # MI355X published FP64 vector peak
 PEAK_HBM = 8.0e12             # MI355X HBM3E, B/s
 
 
@@ -346,6 +347,7 @@ def main():
     fin_ms = kt["finalize"][0] / max(kt["finalize"][1], 1)
     rein_ms = kt["reinject"][0] / max(kt["reinject"][1], 1)
     achieved = FLOP_PER_PAIR * N * (N - 1) / (pair_ms * 1e-3)
+    peak = PEAK_FP64 if prec else PEAK_FP32
     push_gbs = push_bytes_per_ion(prec) * N / (push_ms * 1e-3)
     q, _ = sysm.charges()
     res = {
@@ -371,11 +373,11 @@ def main():
         "roofline": {
             "bound": "alu",
             "achieved": achieved / 1e12,
-            "peak": PEAK_FP32 / 1e12,
+            "peak": peak / 1e12,
             "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32,
+            "frac": achieved / peak,
             "traffic": None if prec else measured_traffic("pair", N),
-            "kernel": "pair_forces",
+            "kernel": "pair_forces_f64" if prec else "pair_forces",
             "flop_per_pair": FLOP_PER_PAIR,
             "launch_ms": pair_ms,
         },
