@@ -234,7 +234,8 @@ od_status od_get_accelerations(od_system* sys, void* a_host);
  * one-sided kernel.  A pair closer than about 4e-6 of the mean ion spacing
  * overflows the range and is reported as OD_ENUMERIC.
  * OD_PAIR_AUTO (the default) takes the symmetric kernel, which is the faster
- * one at every size (1.6x at 2^18 and 2.4x at 2^12 ions on MI355X).
+ * one at every size (1.5x at 2^20, 1.8x at 2^18 and 2.4x at 2^12 ions on
+ * MI355X).
  * The symmetric kernel needs 24 bytes per ion of accumulators.  FP64 systems
  * and the test-particle mode always use the one-sided kernel; a cutoff
  * (od_set_cutoff) takes precedence over either.  od_get_pair_kernel reports
