@@ -2,18 +2,20 @@
 //
 // The screened Coulomb force is antisymmetric, so the tile pair (I, J) of
 // 256-ion target and source tiles also gives the reaction on the sources.
-// Work items are runs of tiles J in [J0, J1) of one target tile row I
-// (J >= I), longest first.  Within an item:
-//   * the diagonal tile (J == I) is summed one-sided (each ordered pair);
+// Work items are runs of tiles J in [J0, J1) of kSymRows consecutive target
+// tile rows I .. I + kSymRows - 1 (J >= I), longest first; small systems take
+// one target row per item.  Within an item:
+//   * the rows' own tiles (J < I + kSymRows) go one row at a time, with the
+//     diagonal tile (J == I) summed one-sided (each ordered pair);
 //   * an off-diagonal tile is cut into four sub-tiles of 64 sources; lane l of
-//     a wave pairs its target with source (l + k) mod 64 in step k, adds the
-//     term to its own sum and subtracts it from a source accumulator that
-//     moves one lane down each step (a wavefront rotate), so that after 64
-//     steps every lane holds the reaction on one source, summed over the
-//     wave's 64 targets in a fixed order; the four waves' sums are added in
-//     LDS in a fixed order;
+//     a wave holds one target of every row of the item and meets source
+//     (l + k) mod 64 in step k, adds each term to that target's sum and
+//     subtracts it from a source accumulator that moves one lane down each
+//     step (a wavefront rotate), so that after 64 steps every lane holds the
+//     reaction on one source, summed over the wave's targets in a fixed
+//     order; the four waves' sums are added in LDS in a fixed order;
 //   * reactions go to the sources' int64 fixed-point accumulators once per
-//     tile pair, and the targets' sum once per item.
+//     tile, and the targets' sums once per item.
 // Fixed-point integer addition is exact and commutative, so the totals do
 // not depend on the order in which items run: results are deterministic.
 // A per-ion epilogue kernel converts the totals, adds the grain, drive and
