@@ -40,7 +40,6 @@ constexpr int kPairTile = 256;
 constexpr int kPad = 256;
 constexpr int kReinjGrid = 2 * odk::kSlots;   // a multiple of the lost-list segments
 constexpr int kMaxSplitSingle = 4;             // source splits of one system's pair sum
-constexpr int kSymMinTiles = 1;               // all-pairs sum with each pair once: at every size
 constexpr double kSymItemsTarget = 65536.0;    // work items of the symmetric sum
 constexpr double kSymMinGroupedItems = 2048.0; // fewer grouped items: one target row per item
 constexpr int kConfNr = 32, kConfNz = 32;      // intervals of the confinement grid along r, z
@@ -235,12 +234,12 @@ od_status setup_sym(od_system* s)
     return OD_OK;
 }
 
-// Chooses the all-pairs kernel for the system's kind and size.
+// Chooses the all-pairs kernel for the system's kind: the symmetric one
+// unless one-sided is asked for (it is the faster at every size).
 od_status apply_pair_kind(od_system* s)
 {
     const bool able = s->prec == OD_PREC_FP32 && s->pa.ion_ion;
-    const bool want = able && (s->pair_kind == OD_PAIR_SYMMETRIC ||
-                               (s->pair_kind == OD_PAIR_AUTO && s->Npad / kPairBlock >= kSymMinTiles));
+    const bool want = able && (s->pair_kind == OD_PAIR_SYMMETRIC || s->pair_kind == OD_PAIR_AUTO);
     if (want && !s->sym) {
         od_status st = setup_sym(s);
         if (st != OD_OK) return st;

@@ -139,11 +139,12 @@ def test_batch_symmetric_graph_and_oracle(B):
         say("batch member, symmetric", shadow_step(m, o, ws[1]))
 
 
-@pytest.mark.parametrize("n_ions", [(1 << 16) + 600, (1 << 16) + 412])
+@pytest.mark.parametrize("n_ions", [(1 << 16) + 600, (1 << 16) + 412, (1 << 16) + 900])
 def test_grouped_rows_sampled_parity(B, n_ions):
     """Systems large enough for items of three target rows (259 tiles: one
-    row left over; 258 tiles: none), both with a ragged last tile: sampled
-    accelerations against the oracle, the last 600 ions included."""
+    row left over; 258 tiles: none; 260 tiles: two), each with a ragged last
+    tile: sampled accelerations against the oracle, the last 600 ions
+    included."""
     w = W.single_grain_small().with_(n_ions=n_ions)
     say("grouped rows, N", n_ions)
     with B.System(w) as s:
