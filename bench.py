@@ -192,6 +192,47 @@ def crossover_bench(args):
     print(json.dumps(res), flush=True)
 
 
+def graph_bench(args):
+    """Step time of small single systems launched kernel by kernel against
+    the same steps replayed as HIP graphs of 10 steps (od_set_graph)."""
+    import torch
+    from paper_2205_06557_amd import binding as B
+    from paper_2205_06557_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    K = 200
+    rows = []
+    for n in (2000, 1 << 12, 1 << 14, 1 << 16):
+        w = W.single_grain_small().with_(n_ions=n)
+        row = {"n_ions": n}
+        for name, g in (("single_launch_ms", 0), ("graph_ms", 10)):
+            s = B.System(w, stream=stream.cuda_stream)
+            s.set_graph(g)
+            s.step(20)
+            s.sync()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.step(K)
+            s.sync()
+            row[name] = 1e3 * (time.perf_counter() - t0) / K
+            s.close()
+        row["speedup"] = row["single_launch_ms"] / row["graph_ms"]
+        rows.append(row)
+        print(f"[bench] graph N={n}: {row['single_launch_ms']:.4f} ms/step single launches, "
+              f"{row['graph_ms']:.4f} ms/step graph", file=sys.stderr, flush=True)
+    res = {
+        "metric": "ms per step of small single systems, single launches vs HIP-graph replay",
+        "value": rows[0]["graph_ms"], "unit": "ms", "n_gpus": 1, "steps": K, "warmup": 20,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "one 5 um grain, R = 3 r_De, H = 6 r_De, Mach 1, nu = 0.1 omega_pi",
+                   "n_ions": rows[0]["n_ions"], "steps_per_graph": 10},
+        "series": rows,
+    }
+    print(json.dumps(res), flush=True)
+
+
 def batch_bench(args):
     """Batched sweep: 64 single-grain systems, log2 N ~ U(14, 17), Mach, radius
     and collision frequency drawn per system; one launch per phase for all
@@ -281,7 +322,12 @@ def main():
                     help="the batched 64-system sweep instead of the 2^20-ion two-grain workload")
     ap.add_argument("--crossover", action="store_true",
                     help="pair-phase times of the one-sided and symmetric kernels, 2^12 .. 2^20 ions")
+    ap.add_argument("--graph", action="store_true",
+                    help="small single systems: single launches against HIP-graph replay")
     args = ap.parse_args()
+    if args.graph and args.gpus == 1:
+        graph_bench(args)
+        return
     if args.crossover and args.gpus == 1:
         crossover_bench(args)
         return

@@ -274,6 +274,18 @@ od_status od_rng_block(uint64_t seed, uint64_t system, const uint64_t* ctr_host,
 od_status od_set_timing(od_system* sys, int32_t enable);
 od_status od_get_kernel_times(od_system* sys, double* ms_host, int64_t* launches_host);
 
+/* Capture steps_per_graph (0..1000; 0: no graph) whole steps as one HIP graph
+ * that od_step replays (n_steps / steps_per_graph replays, the remainder
+ * launched one kernel at a time), for systems whose steps are short enough
+ * for launch costs to matter.  The graph is captured on the system's stream,
+ * which must not be the null stream (pass one to od_init_system; else
+ * OD_ESTATE).  Results equal those of the same steps launched one at a time,
+ * bit for bit.  od_set_state, od_set_cutoff, od_set_pair_kernel and
+ * od_set_pair_split drop the graph and the next od_step captures it again;
+ * while timing is on (od_set_timing) steps are launched one at a time so
+ * that the per-kernel times stay meaningful.  Synchronizes the stream. */
+od_status od_set_graph(od_system* sys, int32_t steps_per_graph);
+
 /* ---- batches of independent systems ------------------------------------ */
 
 /* Many independent dust systems (each one the model above, with its own

@@ -103,13 +103,14 @@ def lib():
         L.od_set_pair_kernel.argtypes = [vp, C.c_int32]
         L.od_get_pair_kernel.argtypes = [vp, C.POINTER(C.c_int32)]
         L.od_get_cutoff_info.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
+        L.od_set_graph.argtypes = [vp, C.c_int32]
         for name in ("od_init_system", "od_step", "od_sync", "od_get_dust_charges",
                      "od_get_dust_forces", "od_get_units", "od_get_sizes", "od_get_state",
                      "od_set_state", "od_get_accelerations", "od_get_step_events",
                      "od_rng_block", "od_set_timing", "od_get_kernel_times",
                      "od_get_confinement", "od_set_cutoff", "od_get_cutoff_info",
                      "od_set_pair_split", "od_get_pair_split", "od_set_pair_kernel",
-                     "od_get_pair_kernel"):
+                     "od_get_pair_kernel", "od_set_graph"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -300,6 +301,11 @@ class System:
     # --- timing -------------------------------------------------------------
     def set_timing(self, enable: bool):
         _check(lib().od_set_timing(self._h, 1 if enable else 0))
+
+    def set_graph(self, steps_per_graph: int):
+        """Replay steps_per_graph steps as one HIP graph (0: off); needs a
+        system created on a stream other than the null stream."""
+        _check(lib().od_set_graph(self._h, int(steps_per_graph)))
 
     def kernel_times(self):
         ms = np.zeros(len(KERNEL_CLASSES))

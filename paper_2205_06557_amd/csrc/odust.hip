@@ -88,6 +88,10 @@ struct SysConsts {
 
 struct od_system {
     hipStream_t stream = nullptr;
+    // steps captured as one HIP graph (od_set_graph); re-captured on demand
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int graph_steps = 0;
     od_allocator alloc{};
     bool custom_alloc = false;
     od_plasma pl{};
@@ -526,13 +530,42 @@ hipEvent_t next_event(od_system* s)
     return s->evpool[s->evnext++];
 }
 
-od_status launch_step(od_system* s)
+od_status launch_step(od_system* s, bool timed);
+
+void drop_graph(od_system* s)
+{
+    if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
+    s->gexec = nullptr;
+    s->graph = nullptr;
+}
+
+// Captures s->graph_steps steps of the system's stream as one graph.
+od_status capture_graph(od_system* s)
+{
+    drop_graph(s);
+    HIPCHK(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < s->graph_steps; ++k) {
+        od_status st = launch_step(s, false);
+        if (st != OD_OK) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(s->stream, &g);
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+    }
+    HIPCHK(hipStreamEndCapture(s->stream, &s->graph));
+    HIPCHK(hipGraphInstantiate(&s->gexec, s->graph, nullptr, nullptr, 0));
+    return OD_OK;
+}
+
+od_status launch_step(od_system* s, bool timed)
 {
     const int gp = (int)(s->Npad / kPairBlock);
     const int gq = (int)((s->N + 255) / 256);
     for (int k = 0; k < 4; ++k) {
         int e0 = -1, e1 = -1;
-        if (s->timing) {
+        if (timed) {
             e0 = (int)s->evnext;
             hipEvent_t e = next_event(s);
             if (!e) return fail(OD_EDEVICE, "hipEventCreate failed");
@@ -585,7 +618,7 @@ od_status launch_step(od_system* s)
             odk::finalize_kernel<<<1, 64, 0, s->stream>>>(s->fa, s->ds, s->ctl);
         }
         HIPCHK(hipGetLastError());
-        if (s->timing) {
+        if (timed) {
             e1 = (int)s->evnext;
             hipEvent_t e = next_event(s);
             if (!e) return fail(OD_EDEVICE, "hipEventCreate failed");
@@ -719,10 +752,31 @@ od_status od_step(od_system* s, int64_t n_steps)
 {
     if (!s) return fail(OD_EINVAL, "null system");
     if (n_steps < 0) return fail(OD_EINVAL, "n_steps < 0");
-    for (int64_t k = 0; k < n_steps; ++k) {
-        od_status st = launch_step(s);
+    int64_t left = n_steps;
+    if (s->graph_steps > 0 && !s->timing) {
+        if (!s->gexec && left >= s->graph_steps) {
+            od_status st = capture_graph(s);
+            if (st != OD_OK) return st;
+        }
+        for (; s->gexec && left >= s->graph_steps; left -= s->graph_steps)
+            HIPCHK(hipGraphLaunch(s->gexec, s->stream));
+    }
+    for (; left > 0; --left) {
+        od_status st = launch_step(s, s->timing);
         if (st != OD_OK) return st;
     }
+    return OD_OK;
+}
+
+od_status od_set_graph(od_system* s, int32_t steps_per_graph)
+{
+    if (!s) return fail(OD_EINVAL, "null system");
+    if (steps_per_graph < 0 || steps_per_graph > 1000) return fail(OD_EINVAL, "steps_per_graph out of [0,1000]");
+    if (steps_per_graph > 0 && s->stream == nullptr)
+        return fail(OD_ESTATE, "graph capture needs a stream of the system's own (not the null stream)");
+    HIPCHK(hipStreamSynchronize(s->stream));
+    drop_graph(s);
+    s->graph_steps = steps_per_graph;
     return OD_OK;
 }
 
@@ -766,6 +820,7 @@ void od_destroy(od_system* s)
 {
     if (!s) return;
     (void)hipStreamSynchronize(s->stream);
+    drop_graph(s);
     free_cutoff(s);
     free_sym(s);
     dev_free(s, s->x);
@@ -782,6 +837,7 @@ od_status od_set_cutoff(od_system* s, double r_switch, double r_cut)
 {
     if (!s) return fail(OD_EINVAL, "null system");
     HIPCHK(hipStreamSynchronize(s->stream));
+    drop_graph(s);
     if (!(r_cut > 0.0)) {
         if (s->cut) free_cutoff(s);
         return OD_OK;
@@ -932,6 +988,8 @@ od_status od_set_state(od_system* s, const void* x, const void* v, const double*
     if (q)
         for (int d = 0; d < s->nd; ++d)
             if (!std::isfinite(q[d])) return fail(OD_ENUMERIC, "non-finite charge");
+    HIPCHK(hipStreamSynchronize(s->stream));
+    drop_graph(s);
     const size_t row = (size_t)N * s->esz;
     const size_t drow = (size_t)s->Npad * s->esz;
     for (int c = 0; c < 3; ++c) {
@@ -980,6 +1038,7 @@ od_status od_set_pair_kernel(od_system* s, int32_t kind)
     if (kind == OD_PAIR_SYMMETRIC && (s->prec != OD_PREC_FP32 || !s->pa.ion_ion))
         return fail(OD_EINVAL, "the symmetric sum needs FP32 and the ion-ion force");
     HIPCHK(hipStreamSynchronize(s->stream));
+    drop_graph(s);
     const int old = s->pair_kind;
     s->pair_kind = kind;
     od_status st = apply_pair_kind(s);
@@ -1003,6 +1062,7 @@ od_status od_set_pair_split(od_system* s, int32_t nsplit)
     if (s->prec != OD_PREC_FP32 && nsplit != 1) return fail(OD_EINVAL, "the FP64 mode does not split");
     if (nsplit > s->Npad / kPairBlock) return fail(OD_EINVAL, "more splits than source tiles");
     HIPCHK(hipStreamSynchronize(s->stream));
+    drop_graph(s);
     s->nsplit = nsplit;
     return OD_OK;
 }

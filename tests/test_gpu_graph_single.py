@@ -1,0 +1,108 @@
+"""HIP-graph replay of single-system steps (od_set_graph): every replay equals
+the same steps launched one kernel at a time, bit for bit, for each pair
+kernel; a state change drops the graph and the next step captures it again;
+timing falls back to single launches; the null stream is refused."""
+import numpy as np
+import pytest
+
+from paper_2205_06557_amd import workloads as W
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+LAM = W.single_grain_small().lam
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2205_06557_amd import binding
+    binding.lib()
+    return binding
+
+
+def _snap(s):
+    x, v, q, step = s.get_state()
+    return [np.array(x), np.array(v), np.array(q), np.array([step]), np.array(s.forces(0)),
+            np.array(s.accelerations())]
+
+
+def _same(a, b, what):
+    for k, (u, v) in enumerate(zip(a, b)):
+        assert np.array_equal(u, v), (what, k)
+
+
+@pytest.mark.parametrize("kind", ["symmetric", "one_sided", "cutoff"])
+def test_graph_replays_equal_single_launches(B, kind):
+    import torch
+    w = W.two_grain_wake().with_(n_ions=3000)
+    st = torch.cuda.Stream()                     # default priority
+    say("graph replay,", kind)
+    with B.System(w, stream=st.cuda_stream) as g, B.System(w, stream=st.cuda_stream) as e:
+        for s in (g, e):
+            if kind == "one_sided":
+                s.set_pair_kernel(B.PAIR_ONE_SIDED)
+            if kind == "cutoff":
+                s.set_cutoff(1.5 * LAM, 2.5 * LAM)
+        g.set_graph(4)
+        for rep in range(3):                     # 2 replays + 1 single step each round
+            g.step(9)
+            e.step(9)
+            g.sync()
+            e.sync()
+            _same(_snap(g), _snap(e), (kind, "round", rep))
+            torch.zeros(1000, device="cuda").sum().item()   # unrelated eager work between replays
+        # replacing the state drops the graph; the next step captures it again
+        x, v, q, step = e.get_state()
+        g.set_state(x, v, q, step)
+        g.step(8)
+        e.step(8)
+        g.sync()
+        e.sync()
+        _same(_snap(g), _snap(e), (kind, "after set_state"))
+        # a pair-kernel change drops it too
+        if kind == "symmetric":
+            for s in (g, e):
+                s.set_pair_kernel(B.PAIR_ONE_SIDED)
+            g.step(5)
+            e.step(5)
+            g.sync()
+            e.sync()
+            _same(_snap(g), _snap(e), (kind, "after set_pair_kernel"))
+
+
+def test_graph_with_timing_launches_singly(B):
+    import torch
+    w = W.single_grain_small()
+    st = torch.cuda.Stream()
+    with B.System(w, stream=st.cuda_stream) as g, B.System(w, stream=st.cuda_stream) as e:
+        g.set_graph(5)
+        g.set_timing(True)
+        g.step(10)
+        g.sync()
+        kt = g.kernel_times()
+        assert kt["pair"][1] == 10 and kt["push"][1] == 10      # per-kernel launches, no graph
+        g.set_timing(False)
+        g.step(10)
+        e.step(20)
+        g.sync()
+        e.sync()
+        _same(_snap(g), _snap(e), "timing")
+
+
+def test_graph_errors(B):
+    w = W.single_grain_small()
+    with B.System(w, stream=0) as s:             # the null stream cannot be captured
+        with pytest.raises(B.OdError) as ex:
+            s.set_graph(4)
+        assert ex.value.status == B.OD_ESTATE
+        s.set_graph(0)                           # switching it off is always allowed
+    import torch
+    st = torch.cuda.Stream()
+    with B.System(w, stream=st.cuda_stream) as s:
+        for bad in (-1, 1001):
+            with pytest.raises(B.OdError):
+                s.set_graph(bad)
+        s.set_graph(3)
+        s.step(2)                                # fewer steps than a graph: single launches
+        s.sync()
+        assert s.get_state()[3] == 2
