@@ -26,6 +26,7 @@
 #include "kernels.hpp"
 #include "cutoff.hpp"
 #include "pairsym.hpp"
+#include "worksplit.hpp"
 
 namespace {
 
@@ -40,8 +41,6 @@ constexpr int kPairTile = 256;
 constexpr int kPad = 256;
 constexpr int kReinjGrid = 2 * odk::kSlots;   // a multiple of the lost-list segments
 constexpr int kMaxSplitSingle = 4;             // source splits of one system's pair sum
-constexpr double kSymItemsTarget = 65536.0;    // work items of the symmetric sum
-constexpr double kSymMinGroupedItems = 2048.0; // fewer grouped items: one target row per item
 constexpr int kConfNr = 32, kConfNz = 32;      // intervals of the confinement grid along r, z
 constexpr int kConfNodes = (kConfNr + 1) * (kConfNz + 1);
 
@@ -181,41 +180,6 @@ void free_sym(od_system* s)
     s->sym_items = nullptr;
     s->n_sym_items = 0;
     s->sym = false;
-}
-
-// Work items of the symmetric sum of one system of T tiles: groups of
-// kSymRows target tile rows, each group with runs of at most C source tiles
-// from its first row on (rows left over at the end alone), C chosen for about
-// kSymItemsTarget items.  Where grouping leaves fewer than kSymMinGroupedItems
-// items (small systems, too few to fill the chip), one target row per item
-// instead.  The split depends on T only, so a system's sums are grouped the
-// same way alone and in a batch.
-std::vector<odk::SymItem> sym_items_of(int T)
-{
-    constexpr int R = odk::kSymRows;
-    const double pairs = 0.5 * (double)T * (T + 1);
-    std::vector<odk::SymItem> v;
-    const int C = (int)std::max((double)R, std::ceil(pairs / (R * kSymItemsTarget)));
-    int I = 0;
-    for (; I + R <= T; I += R)
-        for (int J0 = I; J0 < T; J0 += C) v.push_back({I, J0, std::min(J0 + C, T), R});
-    for (; I < T; ++I) v.push_back({I, I, T, 1});
-    if ((double)v.size() >= kSymMinGroupedItems) return v;
-    v.clear();
-    const int C1 = (int)std::max(1.0, std::ceil(pairs / kSymItemsTarget));
-    for (I = 0; I < T; ++I)
-        for (int J0 = I; J0 < T; J0 += C1) v.push_back({I, J0, std::min(J0 + C1, T), 1});
-    return v;
-}
-
-// Longest items first, so that the short ones fill the tail.
-std::vector<odk::SymItem> sym_items(int T)
-{
-    std::vector<odk::SymItem> v = sym_items_of(T);
-    std::stable_sort(v.begin(), v.end(), [](const odk::SymItem& a, const odk::SymItem& b) {
-        return a.J1 - a.J0 > b.J1 - b.J0;
-    });
-    return v;
 }
 
 od_status setup_sym(od_system* s)

@@ -1,0 +1,53 @@
+// worksplit.hpp -- host side: how the symmetric all-pairs sum of one system
+// is cut into work items (pair_sym_kernel, pair_sym_batch_kernel).  Kept
+// apart from the rest of the host code because, with the kernels, it fixes
+// what the pair phase reads and writes.
+#pragma once
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "pairsym.hpp"
+
+namespace {
+
+constexpr double kSymItemsTarget = 65536.0;    // work items of the symmetric sum
+constexpr double kSymMinGroupedItems = 2048.0; // fewer grouped items: one target row per item
+
+// Work items of the symmetric sum of one system of T tiles: groups of
+// kSymRows target tile rows, each group with runs of at most C source tiles
+// from its first row on (rows left over at the end alone), C chosen for about
+// kSymItemsTarget items.  Where grouping leaves fewer than kSymMinGroupedItems
+// items (small systems, too few to fill the chip), one target row per item
+// instead.  The split depends on T only, so a system's sums are grouped the
+// same way alone and in a batch.
+std::vector<odk::SymItem> sym_items_of(int T)
+{
+    constexpr int R = odk::kSymRows;
+    const double pairs = 0.5 * (double)T * (T + 1);
+    std::vector<odk::SymItem> v;
+    const int C = (int)std::max((double)R, std::ceil(pairs / (R * kSymItemsTarget)));
+    int I = 0;
+    for (; I + R <= T; I += R)
+        for (int J0 = I; J0 < T; J0 += C) v.push_back({I, J0, std::min(J0 + C, T), R});
+    for (; I < T; ++I) v.push_back({I, I, T, 1});
+    if ((double)v.size() >= kSymMinGroupedItems) return v;
+    v.clear();
+    const int C1 = (int)std::max(1.0, std::ceil(pairs / kSymItemsTarget));
+    for (I = 0; I < T; ++I)
+        for (int J0 = I; J0 < T; J0 += C1) v.push_back({I, J0, std::min(J0 + C1, T), 1});
+    return v;
+}
+
+// Longest items first, so that the short ones fill the tail.
+std::vector<odk::SymItem> sym_items(int T)
+{
+    std::vector<odk::SymItem> v = sym_items_of(T);
+    std::stable_sort(v.begin(), v.end(), [](const odk::SymItem& a, const odk::SymItem& b) {
+        return a.J1 - a.J0 > b.J1 - b.J0;
+    });
+    return v;
+}
+
+}  // namespace
