@@ -110,6 +110,50 @@ __device__ inline void gauss2(double ua, double ub, double& g1, double& g2)
 }
 
 // ---------------------------------------------------------------------------
+// FP64 pieces of the screened pair term without a division.
+//
+// 1/sqrt(x), x > 0: the hardware estimate (about 24 correct bits) and one
+// third-order Newton-Raphson correction, y (1 + e/2 + 3e^2/8) with
+// e = 1 - x y^2 (the series of (1 - e)^(-1/2)), which triples the correct
+// bits (measured on gfx950 within 1.3 ulp).
+__device__ inline double rsq_f64(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-(x * y), y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
+// e^(-r) for r >= 0 (large r clamped, where the result is 0 in FP64):
+// Cody-Waite reduction r = n ln2 - f with ln 2 split into a 32-bit head
+// (n * head exact) and its remainder, |f| <= ln2 / 2, then the Taylor
+// polynomial of e^f to degree 13 (remainder below 1e-17) by Horner, scaled
+// by 2^n (measured on gfx950 within 1.3 ulp).
+__device__ inline double exp_neg_f64(double r)
+{
+    const double kLog2e = 1.4426950408889634;
+    const double kLn2Hi = 0.6931471803691238;         // ln 2 to 32 significant bits
+    const double kLn2Lo = 1.9082149292705877e-10;     // ln 2 - kLn2Hi
+    const double x = -fmin(r, 800.0);
+    const double n = rint(x * kLog2e);
+    const double f = fma(-n, kLn2Lo, fma(-n, kLn2Hi, x));
+    double p = 1.6059043836821613e-10;                // 1/13!
+    p = fma(p, f, 2.08767569878681e-09);              // 1/12!
+    p = fma(p, f, 2.505210838544172e-08);             // 1/11!
+    p = fma(p, f, 2.755731922398589e-07);             // 1/10!
+    p = fma(p, f, 2.7557319223985893e-06);            // 1/9!
+    p = fma(p, f, 2.48015873015873e-05);              // 1/8!
+    p = fma(p, f, 0.0001984126984126984);             // 1/7!
+    p = fma(p, f, 0.001388888888888889);              // 1/6!
+    p = fma(p, f, 0.008333333333333333);              // 1/5!
+    p = fma(p, f, 0.041666666666666664);              // 1/4!
+    p = fma(p, f, 0.16666666666666666);               // 1/3!
+    p = fma(p, f, 0.5);
+    p = fma(p, f, 1.0);
+    p = fma(p, f, 1.0);
+    return ldexp(p, (int)n);
+}
+
+// ---------------------------------------------------------------------------
 // Wave64 reduction of a double (butterfly over xor masks).
 __device__ inline double wave_sum(double v)
 {

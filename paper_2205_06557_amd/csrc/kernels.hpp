@@ -279,9 +279,11 @@ __global__ __launch_bounds__(BLOCK) void pair_forces_f64(const double* __restric
             for (int k = 0; k < TJ; ++k) {
                 const double4 q = tile[k];
                 const double dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
-                const double r2 = dx * dx + dy * dy + dz * dz;
-                const double r = sqrt(r2);
-                double f = (1.0 + r) * exp(-r) / (r2 * r);
+                const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                const double ri = rsq_f64(r2);
+                const double r = r2 * ri;
+                const double e = exp_neg_f64(r);
+                double f = fma(r, e, e) * (ri * ri * ri);         // (1 + r) e^-r / r^3
                 f = (j0 + k == i) ? 0.0 : f;
                 sx += f * dx;
                 sy += f * dy;
