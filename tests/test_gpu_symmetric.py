@@ -32,6 +32,22 @@ def test_shadowed_steps_symmetric(B, n_ions):
         say("  after 30 free steps", shadow_step(s, o, w))
 
 
+@pytest.mark.parametrize("n_ions", [2, 3, 255, 256, 512])
+def test_smallest_and_exact_tile_systems(B, n_ions):
+    """Degenerate and boundary sizes of the symmetric sum: two and three ions
+    (one tile, mostly padding), one ion short of a tile, exactly one and two
+    tiles (no padding): shadowed steps against the oracle."""
+    w = W.single_grain_small().with_(n_ions=n_ions)
+    say("smallest / exact tiles, N", n_ions)
+    with B.System(w) as s:
+        assert s.pair_kernel() == B.PAIR_SYMMETRIC
+        o = O.Oracle(w)
+        for k in range(3):
+            say("  step", k, shadow_step(s, o, w))
+        s.step(20)
+        say("  after 20 free steps", shadow_step(s, o, w))
+
+
 def test_two_grains_symmetric(B):
     w = W.two_grain_wake().with_(n_ions=5000)
     with B.System(w) as s:
