@@ -192,6 +192,47 @@ def crossover_bench(args):
     print(json.dumps(res), flush=True)
 
 
+def paper_case1_bench(args):
+    """The paper's first test case (Table 2: 2^16 ions, one grain with a preset
+    charge, collisionless Mach 1 flow, 3000 steps) run whole: wall time of the
+    3000 steps, for comparison with the run times the paper quotes for its
+    GPUs (context, not a target)."""
+    import torch
+    from paper_2205_06557_amd import binding as B
+    from paper_2205_06557_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    w = W.paper_table2()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = B.System(w)
+    s.sync()
+    setup = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    s.step(w.n_steps)
+    s.sync()
+    run = time.perf_counter() - t1
+    q, _ = s.charges()
+    F = s.forces(1)
+    s.close()
+    n = w.n_ions
+    res = {
+        "metric": "wall time of the paper's test case 1 (Table 2), 3000 steps",
+        "value": run, "unit": "s", "n_gpus": 1, "steps": w.n_steps, "warmup": 0,
+        "ms_per_step": 1e3 * run / w.n_steps, "higher_is_better": False, "scaling": "strong",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "paper Table 2: N = 2^16, grain r = 58.8 um at z = -1 r_De with "
+                               "charge 392,500 e, collisionless Mach 1, R = 3 r_De, H = 6 r_De, "
+                               "dt = 3.5148e-10 s", "n_ions": n},
+        "setup_s": setup,
+        "ion_steps_per_s": n * w.n_steps / run,
+        "pair_interactions_per_s": n * (n - 1) * w.n_steps / run,
+        "grain_charge_e": float(q[0]) / 1.602176634e-19,
+        "time_averaged_force_N": {"orbit_z": float(F[0, 0, 2]), "collect_z": float(F[0, 2, 2])},
+    }
+    print(json.dumps(res), flush=True)
+
+
 def graph_bench(args):
     """Step time of small single systems launched kernel by kernel against
     the same steps replayed as HIP graphs of 10 steps (od_set_graph)."""
@@ -324,7 +365,12 @@ def main():
                     help="pair-phase times of the one-sided and symmetric kernels, 2^12 .. 2^20 ions")
     ap.add_argument("--graph", action="store_true",
                     help="small single systems: single launches against HIP-graph replay")
+    ap.add_argument("--paper-case1", action="store_true",
+                    help="the paper's test case 1 (Table 2) run whole: wall time of 3000 steps")
     args = ap.parse_args()
+    if args.paper_case1 and args.gpus == 1:
+        paper_case1_bench(args)
+        return
     if args.graph and args.gpus == 1:
         graph_bench(args)
         return
