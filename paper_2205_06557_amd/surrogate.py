@@ -204,6 +204,8 @@ def charge_trace(x5, n_ions: int, steps: int, seed: int, q0, every: int = 10):
     for k in range(steps):
         s.step(1)
         tr[k] = s.charges()[0] if (k % every == 0 or k + 1 == steps) else np.nan
+        if (k + 1) % 2000 == 0:
+            print(f"[surrogate]   step {k + 1}/{steps}, {time.time() - t0:.1f} s", flush=True)
     s.sync()
     # fill the unsampled steps by holding the last sample (block means only)
     last = tr[0]
