@@ -45,6 +45,23 @@ def test_shadowed_steps_with_cutoff(B, n_ions, H, r_sw, r_cut):
         assert ns in (max(1, k), max(1, k - 1)) and 0 < npairs
 
 
+def test_cutoff_with_confinement_and_field_driven(B):
+    """Every option of the paper at once: the ion-ion cutoff, the confinement
+    field of Appendix A and the field-driven injection distribution, shadowed
+    against the oracle with the same options."""
+    w = W.single_grain_small().with_(n_ions=5000, H=12 * LAM,
+                                     flags=W.FLAG_CONFINEMENT | W.FLAG_FIELD_DRIVEN)
+    say("cutoff + confinement + field-driven")
+    with B.System(w) as s:
+        s.set_cutoff(2.0 * LAM, 3.0 * LAM)
+        o = O.Oracle(w)
+        o.set_cutoff(2.0 * LAM, 3.0 * LAM)
+        for k in range(3):
+            say("  step", k, shadow_step(s, o, w))
+        s.step(20)
+        say("  after 20 free steps", shadow_step(s, o, w))
+
+
 def test_far_cutoff_equals_all_pairs(B):
     w = W.single_grain_small().with_(n_ions=4000)
     with B.System(w) as a, B.System(w) as c:
