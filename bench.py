@@ -45,6 +45,24 @@ def measured_traffic(kernel: str, n_ions: int):
     return None if k is None else k["traffic_bytes"]
 
 
+def copy_rate(nbytes: int, reps: int = 20) -> float:
+    """GB/s of a plain device-to-device copy moving `nbytes` in total (read
+    plus write), timed with events: what a transfer of the push kernel's
+    size reaches on this device."""
+    import torch
+    half = max(nbytes // 2, 1)
+    src = torch.empty(half, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    return 2 * half * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+
 def push_bytes_per_ion(prec: int) -> int:
     e = 4 if prec == 0 else 8
     return 3 * e * 3 + 2 * 3 * e + 1      # read x, v, a; write x, v; write event byte
@@ -486,6 +504,7 @@ def main():
         "kernel_ms": {"pair": pair_ms, "push": push_ms, "reinject": rein_ms, "finalize": fin_ms},
         "dust_charge_e": [float(x) / 1.602176634e-19 for x in q],
     }
+    res["push_roofline"]["copy_reference_gbs"] = copy_rate(push_bytes_per_ion(prec) * N)
     if not args.no_cpu:
         print("[bench] timing the CPU oracle on a sample ...", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(w, sysm, args.cpu_seconds)
