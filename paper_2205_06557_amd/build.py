@@ -43,7 +43,30 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    build_c_example(verbose)
     return LIB
+
+
+C_EXAMPLE_SRC = os.path.join(ROOT, "tests", "c_abi_example.c")
+C_EXAMPLE = os.path.join(ROOT, "tests", "c_abi_example")
+
+
+def c_example_command(out: str = C_EXAMPLE) -> list:
+    """gcc line of the C program that uses the library through odust.h only."""
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    return ["gcc", "-std=c11", "-O2", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), C_EXAMPLE_SRC,
+            "-o", out, "-L", HERE, "-lodust", "-Wl,-rpath,$ORIGIN/../paper_2205_06557_amd", "-L", os.path.join(rocm, "lib"),
+            "-Wl,-rpath-link," + os.path.join(rocm, "lib"), "-lm"]
+
+
+def build_c_example(verbose: bool = False) -> str:
+    if not os.path.exists(C_EXAMPLE_SRC):
+        return ""
+    cmd = c_example_command()
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    return C_EXAMPLE
 
 
 if __name__ == "__main__":
