@@ -128,7 +128,8 @@ typedef struct od_system od_system;
  *   allocator: NULL for hipMalloc/hipFree.
  * Errors: OD_EINVAL (N < 2, non-positive sizes or temperatures, a grain that
  * crosses the wall or overlaps another, bad mode/precision/flags),
- * OD_ENOMEM, OD_EDEVICE, OD_ESTATE (an ion could not be placed). */
+ * OD_ENOMEM, OD_EDEVICE (no HIP device visible, or a HIP call failed),
+ * OD_ESTATE (an ion could not be placed). */
 od_status od_init_system(const od_plasma* plasma, const od_sim* sim, const od_dust* dust,
                          int32_t n_dust, void* hip_stream, const od_allocator* allocator,
                          od_system** out);

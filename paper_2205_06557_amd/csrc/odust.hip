@@ -593,6 +593,18 @@ od_status launch_step(od_system* s, bool timed)
     return OD_OK;
 }
 
+// OD_EDEVICE with a plain message when no HIP device is visible, so that a
+// missing GPU is not reported as a failed allocation further on.
+od_status need_device()
+{
+    int nd = 0;
+    if (hipGetDeviceCount(&nd) != hipSuccess || nd < 1) {
+        (void)hipGetLastError();
+        return fail(OD_EDEVICE, "no HIP device is visible");
+    }
+    return OD_OK;
+}
+
 od_status read_status(od_system* s)
 {
     int st = 0;
@@ -620,6 +632,8 @@ od_status od_init_system(const od_plasma* plasma, const od_sim* sim, const od_du
     if (st != OD_OK) return st;
     if (allocator && (!allocator->alloc || !allocator->release))
         return fail(OD_EINVAL, "allocator needs alloc and release");
+    st = need_device();
+    if (st != OD_OK) return st;
     od_system* s = new (std::nothrow) od_system();
     if (!s) return fail(OD_ENOMEM, "host allocation failed");
     s->stream = (hipStream_t)hip_stream;

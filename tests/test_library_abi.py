@@ -58,3 +58,13 @@ def test_null_arguments_rejected():
     assert L.od_sync(None) == B.OD_EINVAL
     assert L.od_get_dust_forces(None, 0, None) == B.OD_EINVAL
     L.od_destroy(None)
+
+
+def test_missing_device_is_reported():
+    """Without a visible GPU, creating a system fails with OD_EDEVICE and a
+    plain message (valid parameters, so the device check is what fails)."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    assert _init(W.single_grain_small()) == B.OD_EDEVICE
+    assert b"no HIP device" in B.lib().od_last_error()
