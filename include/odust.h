@@ -175,7 +175,8 @@ od_status od_get_units(od_system* sys, double* units_host);
  * Eq. (1) stay complete.  Distances in m; r_cut <= 0 returns to the
  * all-pairs sum.  FP32 systems only (OD_EINVAL otherwise); needs
  * 0 <= r_switch < r_cut.  Each step then sorts the ions into slabs along z
- * (width about r_cut / 4, at most 1024 slabs) and evaluates each pair of
+ * (width about r_cut / 16, or r_cut / 8 where that would pass 1024 slabs;
+ * at most 1024) and evaluates each pair of
  * blocks of 256 sorted ions within reach once (both reactions, int64 fixed
  * point as the symmetric all-pairs kernel).
  * Allocates the sort buffers (about 44 bytes per ion plus 4 bytes per slab

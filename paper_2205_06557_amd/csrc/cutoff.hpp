@@ -6,7 +6,8 @@
 // and the force is -d(phi S)/dr; S and S' vanish from r_cut on, so pairs
 // beyond the cutoff contribute exactly zero without a branch.
 //
-// Every step the ions are binned into slabs along z (width w, about r_cut / 4)
+// Every step the ions are binned into slabs along z (width w, about r_cut / 16,
+// or r_cut / 8 in domains long enough to pass kMaxSlabs)
 // and sorted by slab with a stable counting sort (so the order, and with it every
 // floating-point sum, is deterministic):
 //   slab_count_kernel    slab of each ion; per-block slab histogram

@@ -823,8 +823,11 @@ od_status od_set_cutoff(od_system* s, double r_switch, double r_cut)
     if (s->prec != OD_PREC_FP32) return fail(OD_EINVAL, "the cutoff path runs in FP32 only");
     if (!(r_switch >= 0.0) || !(r_switch < r_cut)) return fail(OD_EINVAL, "need 0 <= r_switch < r_cut");
     const double H = s->sim.H / s->lam, rc = r_cut / s->lam, rs = r_switch / s->lam;
-    // slabs of about r_cut / 4 (at most kMaxSlabs), reach = ceil(r_cut / width)
-    const int nslab = (int)std::min<double>(odk::kMaxSlabs, std::max(1.0, std::floor(4.0 * H / rc)));
+    // Slabs of about r_cut / 16, so that the blocks within reach overshoot the
+    // cutoff sphere by little; where that many would pass kMaxSlabs, r_cut / 8
+    // (timed faster there than the capped finer width).  reach = ceil(r_cut / width).
+    const double per = std::floor(16.0 * H / rc) <= odk::kMaxSlabs ? 16.0 : 8.0;
+    const int nslab = (int)std::min<double>(odk::kMaxSlabs, std::max(1.0, std::floor(per * H / rc)));
     const int reach = (int)std::ceil(rc * nslab / H);
     const int nblk = (int)(s->Npad / 256);
     if (s->cut) free_cutoff(s);

@@ -23,9 +23,10 @@ def B():
 
 
 @pytest.mark.parametrize("n_ions,H,r_sw,r_cut", [
-    (2000, 6.0, 1.0, 1.5),          # 4 slabs
-    (8229, 24.0, 1.2, 2.0),         # 12 slabs, ragged N
-    (3000, 6.0, 0.0, 7.0),          # one slab, switching from r = 0
+    (2000, 6.0, 1.0, 1.5),          # 64 slabs
+    (8229, 24.0, 1.2, 2.0),         # 192 slabs, ragged N
+    (3000, 6.0, 0.0, 7.0),          # 13 slabs, all within reach, switching from r = 0
+    (3000, 6.0, 0.0, 100.0),        # one slab
 ])
 def test_shadowed_steps_with_cutoff(B, n_ions, H, r_sw, r_cut):
     w = W.single_grain_small().with_(n_ions=n_ions, H=H * LAM)
@@ -40,8 +41,10 @@ def test_shadowed_steps_with_cutoff(B, n_ions, H, r_sw, r_cut):
         say("  after 20 free steps", shadow_step(s, o, w))
         ns, npairs = s.cutoff_info()
         say("  slabs", ns, "pairs evaluated", npairs, "of", n_ions * n_ions)
-        # about 4 H / r_cut slabs (one fewer if the ratio rounds below an integer)
-        k = int(4 * H // r_cut)
+        # about 16 H / r_cut slabs, 8 H / r_cut where that passes the 1024-slab
+        # limit (one fewer if the ratio rounds below an integer)
+        per = 16 if int(16 * H // r_cut) <= 1024 else 8
+        k = min(1024, int(per * H // r_cut))
         assert ns in (max(1, k), max(1, k - 1)) and 0 < npairs
 
 
