@@ -115,7 +115,7 @@ def cutoff_bench(args):
 
     torch.cuda.set_device(0)
     series = []
-    for lg in range(17, 23):
+    for lg in sorted(int(v) for v in args.cutoff_sizes.split(",")):
         w = W.long_domain(1 << lg)
         s = B.System(w)
         s.set_cutoff(W.CUTOFF_SWITCH, W.CUTOFF_RADIUS)
@@ -141,7 +141,7 @@ def cutoff_bench(args):
               f"{row['sources_per_ion']:.0f} sources per ion", file=sys.stderr, flush=True)
     n = np.array([r["n_ions"] for r in series], dtype=float)
     t = np.array([r["ms_per_step"] for r in series])
-    beta = float(np.polyfit(np.log(n), np.log(t), 1)[0])
+    beta = float(np.polyfit(np.log(n), np.log(t), 1)[0]) if len(series) > 1 else None
     last = series[-1]
     achieved = FLOP_PER_CUT_PAIR * last["pairs_evaluated"] / (last["pair_ms"] * 1e-3)
     res = {
@@ -377,6 +377,8 @@ def main():
                     help="add the confinement field of the outer plasma (Appendix A)")
     ap.add_argument("--cutoff", action="store_true",
                     help="the constant-concentration series with the ion-ion cutoff")
+    ap.add_argument("--cutoff-sizes", default="17,18,19,20,21,22",
+                    help="log2 N of the cutoff series (comma-separated)")
     ap.add_argument("--batch", action="store_true",
                     help="the batched 64-system sweep instead of the 2^20-ion two-grain workload")
     ap.add_argument("--crossover", action="store_true",
