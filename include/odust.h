@@ -297,7 +297,9 @@ od_status od_set_graph(od_system* sys, int32_t steps_per_graph);
  * steps.  Results of a system equal those of the same system run alone
  * with the same pair kernel, bit for bit (for the one-sided kernel, when its
  * pair sum is not split; see od_batch_set_config).
- * FP32 only (sim[s].precision must be OD_PREC_FP32).
+ * FP32 only (sim[s].precision must be OD_PREC_FP32); all-pairs ion-ion sums
+ * only (the cutoff of od_set_cutoff is an option of single systems, whose
+ * long domains fill the chip alone).
  *   plasma_host[n_systems], sim_host[n_systems]: per-system parameters;
  *   dust_host: all grains, system after system; n_dust_host[n_systems];
  *   hip_stream: NULL creates a private non-blocking stream (graph capture
