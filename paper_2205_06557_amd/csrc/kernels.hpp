@@ -251,12 +251,35 @@ void pair_forces_f32(const float* __restrict__ xs,
 }
 
 // Forces, FP64 throughout (precision mode OD_PREC_FP64).
+// FP64 pair terms of one target against a staged tile of TJ sources;
+// Self: the tile holds the target itself (source index `self`), whose term
+// is dropped.
+template <int TJ, bool Self>
+__device__ __forceinline__ void f64_tile(const double4* __restrict__ tile, double xi, double yi, double zi,
+                                         int self, double& sx, double& sy, double& sz)
+{
+    for (int k = 0; k < TJ; ++k) {
+        const double4 q = tile[k];
+        const double dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
+        const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+        const double ri = rsq_f64(r2);
+        const double r = r2 * ri;
+        const double e = exp_neg_f64(r);
+        double f = fma(r, e, e) * (ri * ri * ri);         // (1 + r) e^-r / r^3
+        if (Self) f = (k == self) ? 0.0 : f;
+        sx += f * dx;
+        sy += f * dy;
+        sz += f * dz;
+    }
+}
+
 template <int BLOCK, int TJ>
 __global__ __launch_bounds__(BLOCK) void pair_forces_f64(const double* __restrict__ xs,
                                                          double* __restrict__ acc,
                                                          PairArgs p, DustSet ds,
                                                          Ctl* __restrict__ ctl)
 {
+    static_assert(BLOCK == TJ, "the block's own tile is the one source tile holding its targets");
     __shared__ double4 tile[TJ];
     __shared__ double red[BLOCK / 64][kMaxDust][3];
     const int Npad = p.Npad;
@@ -276,19 +299,10 @@ __global__ __launch_bounds__(BLOCK) void pair_forces_f64(const double* __restric
                 tile[t] = q;
             }
             __syncthreads();
-            for (int k = 0; k < TJ; ++k) {
-                const double4 q = tile[k];
-                const double dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
-                const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-                const double ri = rsq_f64(r2);
-                const double r = r2 * ri;
-                const double e = exp_neg_f64(r);
-                double f = fma(r, e, e) * (ri * ri * ri);         // (1 + r) e^-r / r^3
-                f = (j0 + k == i) ? 0.0 : f;
-                sx += f * dx;
-                sy += f * dy;
-                sz += f * dz;
-            }
+            if (j0 == i0)      // the block's own tile holds the self-pair
+                f64_tile<TJ, true>(tile, xi, yi, zi, threadIdx.x, sx, sy, sz);
+            else
+                f64_tile<TJ, false>(tile, xi, yi, zi, threadIdx.x, sx, sy, sz);
         }
     }
     const bool live = i < p.N;
