@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "odust.hip")
 LIB = os.path.join(HERE, "libodust.so")
-DEPS = [os.path.join(HERE, "csrc", f) for f in ("odust.hip", "kernels.hpp", "device_common.hpp", "batch.hpp", "batch_api.inc", "mlp.hpp", "mlp_api.inc", "cutoff.hpp", "pairsym.hpp", "worksplit.hpp")] + [
+DEPS = [os.path.join(HERE, "csrc", f) for f in ("odust.hip", "kernels.hpp", "device_common.hpp", "batch.hpp", "batch_api.inc", "mlp.hpp", "mlp_api.inc", "cutoff.hpp", "pairsym.hpp", "worksplit.hpp", "symitems.hpp")] + [
     os.path.join(ROOT, "include", "odust.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

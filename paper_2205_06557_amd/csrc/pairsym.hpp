@@ -24,6 +24,7 @@
 #pragma once
 
 #include "kernels.hpp"
+#include "symitems.hpp"
 
 namespace odk {
 
@@ -33,19 +34,12 @@ namespace odk {
 // nearest neighbours, ~ n^(2/3)) while the int64 range keeps a margin of
 // about 1e13 for close pairs.
 
-// Target tile rows that share one pass over the sources (sym_rows), and the
-// occupancy the symmetric kernels are compiled for (75 VGPRs at three rows).
-// Three rows at six waves per SIMD, with the step written as differences,
-// pair terms, then sums, timed fastest among 2 to 4 rows, four statement
-// orders, 16 or 32 unrolled steps and 5 to 8 waves per SIMD on gfx950.
-constexpr int kSymRows = 3;
+// The occupancy the symmetric kernels are compiled for: 75 VGPRs at kSymRows
+// = 3 target rows per item (symitems.hpp).  Three rows at six waves per SIMD,
+// with the step written as differences, pair terms, then sums, timed fastest
+// among 2 to 4 rows, four statement orders, 16 or 32 unrolled steps and 5 to
+// 8 waves per SIMD on gfx950.
 constexpr int kSymWaves = 6;
-
-// rows == 1: target tile row I against source tiles [J0, J1) (sym_item);
-// rows == kSymRows: target tile rows I .. I + kSymRows - 1 together (sym_rows).
-struct SymItem {
-    int I, J0, J1, rows;
-};
 
 // One pair term (1 + r) e^-r / r^3 for the difference d.
 __device__ __forceinline__ float sym_f(float dx, float dy, float dz)

@@ -8,7 +8,7 @@
 #include <cmath>
 #include <vector>
 
-#include "pairsym.hpp"
+#include "symitems.hpp"
 
 namespace {
 

@@ -23,7 +23,7 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ("csrc/kernels.hpp", "csrc/device_common.hpp", "csrc/cutoff.hpp", "csrc/pairsym.hpp",
-                  "csrc/worksplit.hpp")
+                  "csrc/worksplit.hpp", "csrc/symitems.hpp")
 CALIB_BYTES = 1 << 28
 KERNELS = {"pair_forces_f32": "pair", "pair_sym_kernel": "pair", "pair_sym_epilogue": "pair_epilogue",
            "push_kernel<float>": "push", "reinject_kernel<float>": "reinject", "finalize_kernel": "finalize"}
