@@ -48,6 +48,19 @@ def test_smallest_and_exact_tile_systems(B, n_ions):
         say("  after 20 free steps", shadow_step(s, o, w))
 
 
+def test_no_grains_symmetric(B):
+    """A plasma cylinder without grains (n_dust = 0): only the ion-ion sum,
+    the drive and the boundary act; shadowed steps against the oracle."""
+    w = W.single_grain_small().with_(n_ions=3000, dust=[])
+    with B.System(w) as s:
+        assert s.nd == 0 and s.pair_kernel() == B.PAIR_SYMMETRIC
+        o = O.Oracle(w)
+        for k in range(2):
+            say("no grains, step", k, shadow_step(s, o, w))
+        s.step(20)
+        say("no grains, after 20 free steps", shadow_step(s, o, w))
+
+
 def test_two_grains_symmetric(B):
     w = W.two_grain_wake().with_(n_ions=5000)
     with B.System(w) as s:
