@@ -34,11 +34,12 @@ namespace odk {
 // nearest neighbours, ~ n^(2/3)) while the int64 range keeps a margin of
 // about 1e13 for close pairs.
 
-// The occupancy the symmetric kernels are compiled for: 75 VGPRs at kSymRows
-// = 3 target rows per item (symitems.hpp).  Three rows at six waves per SIMD,
-// with the step written as differences, pair terms, then sums, timed fastest
-// among 2 to 4 rows, four statement orders, 16 or 32 unrolled steps and 5 to
-// 8 waves per SIMD on gfx950.
+// The occupancy the symmetric kernels are compiled for, with kSymRows = 3
+// target rows per item (symitems.hpp).  Three rows at six waves per SIMD,
+// with the step written as differences, pair terms, then sums and all 64
+// steps of a sub-tile unrolled, timed fastest among 2 to 4 rows, four
+// statement orders, 16, 32 or 64 unrolled steps and 5 to 8 waves per SIMD
+// on gfx950.
 constexpr int kSymWaves = 6;
 
 // One pair term (1 + r) e^-r / r^3 for the difference d.
@@ -190,7 +191,7 @@ __device__ __forceinline__ void sym_rows(const float* __restrict__ X, const floa
         for (int st = 0; st < 4; ++st) {
             float jx = 0.0f, jy = 0.0f, jz = 0.0f;
             const float4* base = &src[st][lane];
-#pragma unroll 32
+#pragma unroll
             for (int k = 0; k < 64; ++k) {
                 const float4 q = base[k];                     // source (lane + k) mod 64
                 float dx[R], dy[R], dz[R], f[R];
