@@ -42,14 +42,29 @@ def build(force: bool = False) -> str:
     return LIB
 
 
+def sanitizer_command(out: str) -> list:
+    """gcc line of an AddressSanitizer + UBSan build of the oracle (same
+    floating-point flags as build()); load it with ODUST_ORACLE_LIB=out and
+    LD_PRELOAD naming libasan.so and libubsan.so."""
+    return ["gcc", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+            "-fno-sanitize-recover=undefined", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
+            "-fPIC", "-shared", "-std=c11", "-o", out, SRC, "-lm"]
+
+
 _lib = None
 
 
 def lib():
+    """The oracle library: the build next to this file, or, when the
+    environment names one in ODUST_ORACLE_LIB, another build of the same
+    source (for instance one with AddressSanitizer and UBSan, see
+    ``sanitizer_command``)."""
     global _lib
     if _lib is None:
-        build()
-        L = C.CDLL(LIB)
+        alt = os.environ.get("ODUST_ORACLE_LIB")
+        if not alt:
+            build()
+        L = C.CDLL(alt or LIB)
         P = C.c_void_p
         dp = C.POINTER(C.c_double)
         u64p = C.POINTER(C.c_uint64)
