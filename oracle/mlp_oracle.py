@@ -62,3 +62,18 @@ def loss_grad(p, X, T):
     grads.reverse()
     flat = np.concatenate([np.concatenate([gW.ravel(), gb]) for gW, gb in grads])
     return float(np.mean((Y - T) ** 2)), flat
+
+
+def adam_step(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (Kingma & Ba, 2015, Algorithm 1), FP64: moment
+    estimates m, v of the gradient g are updated in place, bias-corrected by
+    1 - b1^t and 1 - b2^t (t >= 1 the step number), and the parameters are
+    returned as p - lr * m_hat / (sqrt(v_hat) + eps)."""
+    g = np.asarray(g, dtype=np.float64)
+    m *= b1
+    m += (1.0 - b1) * g
+    v *= b2
+    v += (1.0 - b2) * g * g
+    m_hat = m / (1.0 - b1 ** t)
+    v_hat = v / (1.0 - b2 ** t)
+    return np.asarray(p, dtype=np.float64) - lr * m_hat / (np.sqrt(v_hat) + eps)

@@ -278,6 +278,16 @@ class Oracle:
         return dict(a=a, ev=ev, hit=hit, Qrec=Qrec[:nd], F=F[:nd], nabs=nabs[:nd],
                     nexit=int(ec[0]), ncoll=int(ec[1]))
 
+    def last_counts(self):
+        """(absorbed counts [nd], collection force of Eq. (3) [nd,3]) of the
+        last step, without copying the per-ion arrays."""
+        nd1 = max(self.nd, 1)
+        F = np.zeros((nd1, 4, 3))
+        nabs = np.zeros(nd1, dtype=np.int64)
+        lib().orc_last_step(self._h, None, None, None, None, _dp(F),
+                            nabs.ctypes.data_as(C.POINTER(C.c_int64)), None)
+        return nabs[: self.nd], F[: self.nd, 2].copy()
+
     def averages(self):
         nd1 = max(self.nd, 1)
         Q = np.zeros(nd1)
