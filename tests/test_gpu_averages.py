@@ -1,0 +1,132 @@
+"""GPU parity of the time-averaged observables (Section 3: the charge q(n) and
+the four force parts of Eqs. (1)-(4) recorded every step, averaged over the
+steps n >= n_discard).
+
+  * P1 over a whole run: all 200 steps of the small single-grain workload are
+    shadowed (the GPU state loaded into the oracle before every step), with
+    n_discard = 100.  The GPU's running averages must equal the oracle's
+    (orc_averages) to the per-step tolerance, and must equal the mean of the
+    GPU's own per-step records from step n_discard on.
+  * P2 (free-running, same seed): the GPU and the oracle each run the 200
+    steps from their own initial state (equal up to FP32 rounding).  The
+    N-body dynamics is chaotic, so the trajectories separate; the time
+    averages must agree within 1 %, judged with the block-bootstrap standard
+    error of each run's mean.  A difference above 1 % whose three standard
+    errors exceed 1 % is reported as statistically unresolved, not as a pass.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2205_06557_amd import workloads as W
+from tests.gpu_util import say, shadow_step
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2205_06557_amd import binding
+    binding.lib()
+    return binding
+
+
+def _block_sem(series, nblocks=10, nboot=2000, seed=0):
+    """Standard error of the mean of a time series by the block bootstrap."""
+    x = np.asarray(series, dtype=np.float64)
+    b = len(x) // nblocks
+    blocks = x[: b * nblocks].reshape(nblocks, b).mean(axis=1)
+    rng = np.random.default_rng(seed)
+    means = blocks[rng.integers(0, nblocks, size=(nboot, nblocks))].mean(axis=1)
+    return float(means.std(ddof=1))
+
+
+def test_shadowed_run_time_averages(B):
+    w = W.single_grain_small().with_(n_discard=100)
+    say("time averages over", w.n_steps, "shadowed steps of", w.name)
+    Qrec, Frec = [], []
+    with B.System(w) as s:
+        o = O.Oracle(w)
+        nmis = 0
+        for n in range(w.n_steps):
+            r = shadow_step(s, o, w)
+            nmis += r["n_ambiguous_mismatch"]
+            ls = o.last_step()
+            Qrec.append(ls["Qrec"])
+            Frec.append(s.forces(0))
+            if n % 50 == 0:
+                say("  step", n, r)
+        q_now, q_avg = s.charges()
+        F_avg = s.forces(1)
+        F_now = s.forces(0)
+    Qo, Fo, nrec = o.averages()
+    say("ambiguous event mismatches over the run:", nmis)
+    assert nrec == w.n_steps - w.n_discard
+    say("q_avg gpu", q_avg, "oracle", Qo)
+    assert np.allclose(q_avg, Qo, rtol=1e-12, atol=0)
+    for d in range(len(w.dust)):
+        for p in range(4):
+            ref = Fo[d, p]
+            err = np.linalg.norm(F_avg[d, p] - ref)
+            say("  part", p, "gpu", F_avg[d, p], "oracle", ref)
+            assert err <= 1e-5 * np.linalg.norm(ref) + 1e-300, (d, p)
+    # the GPU's averages are the means of its own records from step n_discard on
+    Fm = np.mean(Frec[w.n_discard:], axis=0)
+    assert np.allclose(F_avg, Fm, rtol=1e-12, atol=1e-12 * np.abs(Fm).max())
+    assert np.array_equal(F_now, Frec[-1])
+    Qm = np.mean(Qrec[w.n_discard:], axis=0)
+    assert np.allclose(q_avg, Qm, rtol=1e-12, atol=0)
+
+
+def _compare(label, gpu_series, orc_series, rel=0.01):
+    g, o = np.mean(gpu_series, axis=0), np.mean(orc_series, axis=0)
+    scale = max(np.linalg.norm(o), 1e-300)
+    diff = np.linalg.norm(np.atleast_1d(g - o)) / scale
+    sem = 0.0
+    for c in range(np.size(g)):
+        gs = np.asarray(gpu_series).reshape(len(gpu_series), -1)[:, c]
+        os_ = np.asarray(orc_series).reshape(len(orc_series), -1)[:, c]
+        sem += _block_sem(gs) ** 2 + _block_sem(os_) ** 2
+    sem = math.sqrt(sem) / scale
+    if diff <= rel:
+        verdict = "pass"
+    elif 3 * sem > rel and diff <= 5 * sem:
+        verdict = "statistically unresolved"
+    else:
+        verdict = "FAIL"
+    say(f"  {label}: gpu {g} oracle {o} rel diff {diff:.3e} sem {sem:.3e} -> {verdict}")
+    return verdict
+
+
+def test_free_running_time_averages(B):
+    w = W.single_grain_small().with_(n_discard=100)
+    say("free-running", w.n_steps, "steps of", w.name, "on both sides")
+    gF = []
+    with B.System(w) as s:
+        for n in range(w.n_steps):
+            s.step(1)
+            if n >= w.n_discard:
+                gF.append(s.forces(0))
+        q_now, q_avg = s.charges()
+        F_avg = s.forces(1)
+    o = O.Oracle(w)
+    oF = []
+    for n in range(w.n_steps):
+        o.step()
+        if n >= w.n_discard:
+            oF.append(o.last_step()["F"])
+    Qo, Fo, _ = o.averages()
+    assert np.allclose(np.mean(oF, axis=0), Fo, rtol=1e-12, atol=1e-12 * np.abs(Fo).max())
+    assert np.allclose(np.mean(gF, axis=0), F_avg, rtol=1e-12, atol=1e-12 * np.abs(F_avg).max())
+    verdicts = []
+    # the charge: q_avg against the oracle's average (both deterministic
+    # electron-current charging unless an ion is absorbed)
+    diff_q = abs(q_avg[0] / Qo[0] - 1.0)
+    say(f"  charge: gpu {q_avg[0]:.6e} oracle {Qo[0]:.6e} rel diff {diff_q:.3e}")
+    verdicts.append("pass" if diff_q <= 0.01 else "FAIL")
+    names = ["orbit (Eq. 1)", "dust-dust (Eq. 2)", "collection (Eq. 3)", "external (Eq. 4)"]
+    for p in (0, 3):
+        verdicts.append(_compare(names[p], [f[0, p] for f in gF], [f[0, p] for f in oF]))
+    assert "FAIL" not in verdicts, verdicts

@@ -97,3 +97,48 @@ def test_miniature_surrogate_pipeline(B):
         assert np.allclose(q0, Q[0])
         s.step(20)
         s.sync()
+
+
+def test_adam_steps_match_fp64_reference(B):
+    # two od_mlp_train steps (the whole set as one batch, constant learning
+    # rate) against the FP64 Adam of Kingma & Ba fed with the GPU's own
+    # gradients (tight), and the first step with the FP64 reference gradients
+    # (loose: FP32 gradients).  The GPU's training gathers the rows in a
+    # shuffled order, so its gradient differs from od_mlp_loss_grad's by the
+    # summation order (~1e-7 relative), which moves an update noticeably only
+    # where |g| is near Adam's eps = 1e-8 (none is here: min |g| ~ 2e-7).
+    rng = np.random.default_rng(8)
+    net = B.Mlp(6)
+    _identity_norm(net)
+    p0 = (rng.normal(size=M.N_PARAMS) * 0.15).astype(np.float32)
+    net.set_params(p0)
+    # inputs on a 1/64 grid: the [-1, 1] normalisation maps them exactly
+    X = (rng.integers(-64, 65, size=(256, 5)) / 64.0).astype(np.float32)
+    T = rng.normal(size=(256, 16)).astype(np.float32)
+    lr = 1e-3
+    _, g0 = net.loss_grad(X, T)
+    net.train(X, T, epochs=1, batch=256, lr=lr, lr_final=lr, seed=1)
+    p1 = net.params()
+    _, g1 = net.loss_grad(X, T)
+    net.train(X, T, epochs=1, batch=256, lr=lr, lr_final=lr, seed=2)   # moments carried over
+    p2 = net.params()
+    m, v = np.zeros(M.N_PARAMS), np.zeros(M.N_PARAMS)
+    r1 = M.adam_step(p0, g0, m, v, 1, lr)
+    r2 = M.adam_step(p1, g1, m, v, 2, lr)
+    ulp = 2e-7 * np.abs(p0).max()
+    for k, (got, ref) in enumerate(((p1, r1), (p2, r2)), start=1):
+        d = np.abs(got - ref)
+        say("adam step", k, "max", d.max() / lr, "p99.9", np.percentile(d, 99.9) / lr, "(units of lr)")
+        assert d.max() < 2e-3 * lr + ulp
+        assert np.percentile(d, 99.9) < 1e-3 * lr + ulp
+    # the second step depends on the first step's moments: a fresh optimiser
+    # from p1 would move differently
+    fresh = M.adam_step(p1, g1, np.zeros(M.N_PARAMS), np.zeros(M.N_PARAMS), 1, lr)
+    assert np.percentile(np.abs(fresh - r2), 50) > 5e-3 * lr
+    # against FP64 gradients: relative size of the update difference
+    _, gr = M.loss_grad(p0.astype(np.float64), X.astype(np.float64), T.astype(np.float64))
+    rr = M.adam_step(p0, gr, np.zeros(M.N_PARAMS), np.zeros(M.N_PARAMS), 1, lr)
+    d_gpu, d_ref = p1.astype(np.float64) - p0, rr - p0
+    rel = np.linalg.norm(d_gpu - d_ref) / np.linalg.norm(d_ref)
+    say("adam step 1 vs FP64 gradients, relative L2 of the update difference", rel)
+    assert rel < 1e-2
