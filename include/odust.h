@@ -403,6 +403,21 @@ od_status od_mlp_set_normalization(od_mlp* q, const float* in_lo_host, const flo
  * 1 where every input lies inside the normalisation box, else 0 (callers fall
  * back to the full method there). */
 od_status od_mlp_predict(od_mlp* q, const float* X_host, int64_t n, float* Y_host, int32_t* inside_host);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * prediction of od_mlp_predict with X_dev [n][5] (raw units), Y_dev [n][16]
+ * and inside_dev [n] (may be NULL) in device memory, asynchronous on the
+ * network's stream.  It calls no allocating routine: the normalised inputs
+ * and hidden activations go to a fixed device buffer of the library
+ * (OD_MLP_NOALLOC_MAX_ROWS rows, 1.6 MB, one copy per GPU, held until the
+ * process ends; its address is looked up when the first network on that GPU
+ * is created).  Results equal od_mlp_predict's bit for bit.  n must be in
+ * [0, OD_MLP_NOALLOC_MAX_ROWS] (OD_EINVAL otherwise).  Every call on one GPU
+ * uses that GPU's one buffer: calls that overlap in time on one GPU (on
+ * different streams, or from several threads) race and must be ordered by
+ * the caller; calls in one stream are ordered by the stream. */
+#define OD_MLP_NOALLOC_MAX_ROWS 1024
+od_status od_mlp_predict_noalloc(od_mlp* q, const float* X_dev, int64_t n, float* Y_dev, int32_t* inside_dev);
 /* Mean-squared error and its gradient (grad_host[35856]) on n <= 4096 rows of
  * already normalised inputs Xn_host[n][5] and standardised targets
  * Tn_host[n][16]. */

@@ -553,11 +553,13 @@ def _mlp_lib():
         L.od_mlp_set_params.argtypes = [vp, fp]
         L.od_mlp_set_normalization.argtypes = [vp, fp, fp, fp, fp]
         L.od_mlp_predict.argtypes = [vp, fp, i64, fp, C.POINTER(C.c_int32)]
+        L.od_mlp_predict_noalloc.argtypes = [vp, vp, i64, vp, vp]
         L.od_mlp_loss_grad.argtypes = [vp, fp, fp, i64, fp, dp]
         L.od_mlp_train.argtypes = [vp, fp, fp, i64, C.POINTER(TrainCfg), dp]
         L.od_oml_floating_charge.argtypes = [C.POINTER(Plasma), C.c_double, dp]
         for name in ("od_mlp_create", "od_mlp_get_params", "od_mlp_set_params", "od_mlp_set_normalization",
-                     "od_mlp_predict", "od_mlp_loss_grad", "od_mlp_train", "od_oml_floating_charge"):
+                     "od_mlp_predict", "od_mlp_predict_noalloc", "od_mlp_loss_grad", "od_mlp_train",
+                     "od_oml_floating_charge"):
             getattr(L, name).restype = C.c_int
         _mlp_sigs = True
     return L
@@ -619,6 +621,13 @@ class Mlp:
         _check(_mlp_lib().od_mlp_predict(self._h, _ptr(X, C.c_float), n, _ptr(Y, C.c_float),
                                          _ptr(inside, C.c_int32)))
         return Y, inside.astype(bool)
+
+    def predict_noalloc(self, X_dev: int, n: int, Y_dev: int, inside_dev: Optional[int] = None):
+        """od_mlp_predict_noalloc on device addresses (for instance
+        ``tensor.data_ptr()`` of float32 [n,5], float32 [n,16] and int32 [n]
+        tensors); asynchronous on the network's stream."""
+        _check(_mlp_lib().od_mlp_predict_noalloc(self._h, C.c_void_p(X_dev), int(n), C.c_void_p(Y_dev),
+                                                 None if inside_dev is None else C.c_void_p(inside_dev)))
 
     def loss_grad(self, Xn, Tn):
         Xn = _f32(Xn).reshape(-1, 5)
