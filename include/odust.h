@@ -225,7 +225,7 @@ od_status od_set_state(od_system* sys, const void* x_host, const void* v_host, c
  * (float or double as the state). */
 od_status od_get_accelerations(od_system* sys, void* a_host);
 
-/* All-pairs ion-ion kernel (FP32 systems with the ion-ion force).
+/* All-pairs ion-ion kernel (FP32 systems).
  * OD_PAIR_ONE_SIDED evaluates every ordered pair (one target per lane, all
  * sources); OD_PAIR_SYMMETRIC evaluates each unordered pair once and applies
  * the reaction to the source (Newton's third law of the screened Coulomb
@@ -239,9 +239,12 @@ od_status od_get_accelerations(od_system* sys, void* a_host);
  * one at every size (1.5x at 2^20, 1.8x at 2^18 and 2.4x at 2^12 ions on
  * MI355X).
  * The symmetric kernel needs 24 bytes per ion of accumulators.  FP64 systems
- * and the test-particle mode always use the one-sided kernel; a cutoff
- * (od_set_cutoff) takes precedence over either.  od_get_pair_kernel reports
- * the kernel in use. */
+ * always use the one-sided kernel; a cutoff (od_set_cutoff) takes precedence
+ * over either.  In test-particle mode (OD_FLAG_NO_ION_ION) the symmetric
+ * setting runs no pair kernel at all: the step's tail adds the grain, drive
+ * and confinement terms (the one-sided setting adds them in a pair kernel
+ * without ion-ion terms, in FP64).  od_get_pair_kernel reports the kernel in
+ * use. */
 #define OD_PAIR_AUTO 0
 #define OD_PAIR_ONE_SIDED 1
 #define OD_PAIR_SYMMETRIC 2

@@ -21,7 +21,7 @@ OD_OK, OD_EINVAL, OD_EDEVICE, OD_ENUMERIC, OD_ESTATE, OD_ENOMEM = 0, -1, -2, -3,
 PREC_FP32, PREC_FP64 = 0, 1
 PAIR_AUTO, PAIR_ONE_SIDED, PAIR_SYMMETRIC = 0, 1, 2
 EV_NONE, EV_EXIT, EV_ABS_BASE, EV_COLL_BIT = 0, 1, 2, 0x80
-KERNEL_CLASSES = ("pair", "push", "reinject", "finalize")
+KERNEL_CLASSES = ("pair", "tail", "reinject", "finalize")   # finalize runs inside the tail
 
 
 class OdError(RuntimeError):
@@ -358,7 +358,7 @@ def _batch_lib():
     return L
 
 
-BATCH_TIME_CLASSES = ("pair", "push", "reinject", "finalize", "graph")
+BATCH_TIME_CLASSES = ("pair", "tail", "reinject", "finalize", "graph")   # finalize runs inside the tail
 
 
 class Batch:

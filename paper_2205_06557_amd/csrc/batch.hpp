@@ -31,10 +31,10 @@ struct PairItem {
 
 struct BatchCtl {
     unsigned int queue;                 // next pair work item
-    unsigned int pad_;
-    unsigned long long n_lost[kSlots];  // lost-list segment lengths
+    unsigned int lost_ticket;           // reinjection blocks that have finished
+    unsigned int lost_seg[kSlots];      // lost-list segment lengths (all systems)
     int status;
-    int pad2_[11];
+    int pad2_[13];
 };
 
 __device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -83,7 +83,7 @@ void pair_batch_kernel(const float* __restrict__ xs,
 // pairsym.hpp): item = (system, target tile row, source tile run); int64
 // fixed-point totals in fix (planes `plane` apart, system at its offset).
 struct SymBatchItem {
-    int sys, I, J0, J1, rows, pad_[3];
+    int sys, I, J0, J1, rows, st0, st1, pad_;
 };
 
 template <int BLOCK, int TJ>
@@ -100,99 +100,57 @@ void pair_sym_batch_kernel(const float* __restrict__ xs, long long plane, const 
     const long long off = sys[s].off;
     const float* X = xs + off;
     const int I = uniform_int(it.I), J0 = uniform_int(it.J0), J1 = uniform_int(it.J1);
-    sym_dispatch<BLOCK>(X, X + plane, X + 2 * plane, sys[s].pa.N, uniform_int(it.rows), I, J0, J1, fix + off,
-                        plane, sys[s].pa.sym_scale, &ctls[s].status, src, jpart, PlainPair{});
+    sym_dispatch<BLOCK>(X, X + plane, X + 2 * plane, sys[s].pa.N, uniform_int(it.rows), I, J0, J1,
+                        uniform_int(it.st0), uniform_int(it.st1), fix + off, plane, sys[s].pa.sym_scale,
+                        &ctls[s].status, src, jpart, PlainPair{});
 }
 
-// Per ion of every system (block b belongs to system blk_sys[b]): converts
-// the fixed-point totals, adds the pair_epilogue terms, clears the totals.
-__global__ __launch_bounds__(256) void pair_sym_batch_epilogue(const float* __restrict__ xs,
-                                                               float* __restrict__ acc, long long plane,
-                                                               unsigned long long* __restrict__ fix,
-                                                               const SysDesc* sys, Ctl* __restrict__ ctls,
-                                                               const int* __restrict__ blk_sys)
+// The per-ion tail of the step for every system (block b belongs to system
+// blk_sys[b]; see tail_block): FIX for the symmetric pair sums (totals in
+// fix), else the one-sided kernel's acceleration planes.  Block 0 also
+// rewinds the one-sided kernel's work queue, whose pair kernel has finished.
+template <bool FIX>
+__global__ __launch_bounds__(256) void step_tail_batch_kernel(float* __restrict__ xs, float* __restrict__ vs,
+                                                              float* __restrict__ as, long long plane,
+                                                              unsigned long long* __restrict__ fix,
+                                                              uint8_t* __restrict__ ev, const SysDesc* sys,
+                                                              Ctl* __restrict__ ctls,
+                                                              const int* __restrict__ blk_sys, BatchCtl* bc,
+                                                              int2* __restrict__ lost)
 {
-    __shared__ double red[4][kMaxDust][3];
+    if (blockIdx.x == 0 && threadIdx.x == 0) bc->queue = 0u;
     const int s = uniform_int(blk_sys[blockIdx.x]);
     const SysDesc& S = sys[s];
     const long long off = S.off;
-    const int i = (blockIdx.x - S.blk0) * 256 + threadIdx.x;
-    const bool live = i < S.pa.N;
-    const float* X = xs + off;
-    const float xi = X[i], yi = X[plane + i], zi = X[2 * plane + i];
-    double v[3];
-    for (int c = 0; c < 3; ++c) {
-        unsigned long long* a = &fix[c * plane + off + i];
-        v[c] = live ? from_fixed(*a, S.pa.sym_scale) : 0.0;
-        *a = 0ull;
-    }
-    float* o = acc + off;
-    pair_epilogue<256>(xi, yi, zi, i, live, S.pa.Cd * v[0], S.pa.Cd * v[1], S.pa.Cd * v[2], true, S.pa,
-                       S.ds, ctls + s, o, o + plane, o + 2 * plane, red);
+    float* X = xs + off;
+    float* V = vs + off;
+    float* A = as + off;
+    tail_block<float, FIX>(X, X + plane, X + 2 * plane, V, V + plane, V + 2 * plane, A, A + plane, A + 2 * plane,
+                           3 * plane, S.nsplit, FIX ? fix + off : nullptr, plane, ev + off,
+                           (blockIdx.x - S.blk0) * 256, S.pa.Npad / 256, S.pa, S.pu, S.ds, S.fa, ctls + s, s,
+                           LostList{bc->lost_seg, &bc->lost_ticket, lost, lost_cap(gridDim.x)});
 }
 
-// Push of the whole batch: block b belongs to system blk_sys[b].
-__global__ __launch_bounds__(256) void push_batch_kernel(float* __restrict__ xs,
-                                                         float* __restrict__ vs,
-                                                         const float* __restrict__ as,
-                                                         long long plane, uint8_t* __restrict__ ev,
-                                                         int2* __restrict__ lost_list,
-                                                         const SysDesc* sys, Ctl* __restrict__ ctls,
-                                                         const int* __restrict__ blk_sys,
-                                                         BatchCtl* bc)
-{
-    const int s = uniform_int(blk_sys[blockIdx.x]);
-    const SysDesc& S = sys[s];
-    Ctl* ctl = ctls + s;
-    const long long off = S.off;
-    const int i = (blockIdx.x - S.blk0) * 256 + threadIdx.x;
-    const uint64_t n = (uint64_t)ctl->step;
-    bool coll = false, lost = false;
-    uint8_t code = kEvNone;
-    if (i < S.pu.N) {
-        float* X = xs + off;
-        float* V = vs + off;
-        const float* A = as + off;
-        push_ion<float>(X, X + plane, X + 2 * plane, V, V + plane, V + 2 * plane, A, A + plane,
-                        A + 2 * plane, 3 * plane, S.nsplit, i, n, S.pu, S.ds, ctl, code, coll, lost);
-        ev[off + i] = code | (coll ? kEvCollBit : 0);
+// Reinjection of the batch's listed ions (system, ion).
+struct BatchSystems {
+    float* xs;
+    float* vs;
+    long long plane;
+    const SysDesc* sys;
+    const Ctl* ctls;
+    __device__ void operator()(int s, float*& X, float*& V, const PushArgs*& p, const Ctl*& c,
+                               long long& P) const
+    {
+        X = xs + sys[s].off; V = vs + sys[s].off; p = &sys[s].pu; c = ctls + s; P = plane;
     }
-    const long long at = wave_tally(ctl, code, coll, lost, bc->n_lost, seg_cap(gridDim.x));
-    if (lost) lost_list[at] = make_int2(s, i);
-}
+};
 
-// Block b walks segment b mod kSlots of the lost list (grid: a multiple of
-// kSlots); cap: segment capacity of the push grid.
-__global__ __launch_bounds__(64) void reinject_batch_kernel(float* __restrict__ xs,
-                                                            float* __restrict__ vs, long long plane,
-                                                            const int2* __restrict__ lost_list,
-                                                            long long cap, const SysDesc* sys,
-                                                            Ctl* __restrict__ ctls, BatchCtl* bc)
+__global__ __launch_bounds__(64) void reinject_batch_kernel(float* __restrict__ xs, float* __restrict__ vs,
+                                                            long long plane, const SysDesc* sys,
+                                                            const Ctl* __restrict__ ctls, BatchCtl* bc,
+                                                            int2* __restrict__ lost, long long cap)
 {
-    const int slot = blockIdx.x % kSlots, part = blockIdx.x / kSlots, parts = gridDim.x / kSlots;
-    const long long cnt = (long long)bc->n_lost[slot];
-    const int2* seg = lost_list + slot * cap;
-    for (long long k = part * 64 + threadIdx.x; k < cnt; k += (long long)parts * 64) {
-        const int2 e = seg[k];
-        const SysDesc& S = sys[e.x];
-        float* X = xs + S.off;
-        float* V = vs + S.off;
-        reinject_ion<float>(X, X + plane, X + 2 * plane, V, V + plane, V + 2 * plane, e.y,
-                            (uint64_t)ctls[e.x].step, S.pu);
-    }
-}
-
-// One wave per system; block 0 also rewinds the batch's queue and list.
-__global__ __launch_bounds__(64) void finalize_batch_kernel(const SysDesc* sys,
-                                                            Ctl* __restrict__ ctls, BatchCtl* bc)
-{
-    __shared__ double Qs[kMaxDust];
-    const SysDesc& S = sys[blockIdx.x];
-    finalize_sys(S.fa, S.ds, ctls + blockIdx.x, Qs);
-    if (blockIdx.x == 0) {
-        bc->n_lost[threadIdx.x] = 0ull;     // blockDim.x == kSlots
-        if (threadIdx.x == 0) bc->queue = 0u;
-    }
+    reinject_list<float>(LostList{bc->lost_seg, &bc->lost_ticket, lost, cap}, BatchSystems{xs, vs, plane, sys, ctls});
 }
 
 __global__ __launch_bounds__(256) void init_batch_kernel(float* __restrict__ xs,

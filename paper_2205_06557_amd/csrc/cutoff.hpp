@@ -201,7 +201,7 @@ void pair_cut_kernel(const float* __restrict__ xs_sorted, const int* __restrict_
     const int je = start[min(s_hi + c.reach + 1, c.nslab)];
     const int J1 = (je + BLOCK - 1) / BLOCK;
     const SwitchedPair pair{c.rsw, c.inv_sw, -30.0f * c.inv_sw};
-    sym_item<BLOCK>(xs_sorted, xs_sorted + Npad, Z, N, I, I, J1, fix, Npad, p.sym_scale, &ctl->status,
+    sym_item<BLOCK>(xs_sorted, xs_sorted + Npad, Z, N, I, I, J1, 0, 4, fix, Npad, p.sym_scale, &ctl->status,
                     src, jpart, pair);
 }
 

@@ -28,17 +28,19 @@ enum : int { kStNaN = 1, kStPlace = 2, kStOverflow = 4 };
 constexpr double kForceScale = 4294967296.0;    // 2^32: Eq. (1) sums, dimensionless
 constexpr double kMomScale = 4294967296.0;      // 2^32: absorbed velocity sums, c_s
 
-// Event counters are spread over kSlots addresses (slot = block index mod
-// kSlots) so that waves of different blocks do not serialise on one atomic;
-// the lost-ion list is cut into kSlots segments the same way.
+// Counters that every block adds to are spread over kSlots addresses (slot =
+// block index mod kSlots): device-scope atomics on one address serialise, and
+// thousands of blocks adding to one word would take tens of microseconds.
 constexpr int kSlots = 64;
 
 // Layout of one system's control block (device memory, int64/double words).
 struct Ctl {
-    unsigned long long acc[kMaxDust][8];   // [0..2] Eq.(1) sum, [3] absorbed count, [4..6] sum v
+    unsigned long long acc[kMaxDust][8];   // [3] absorbed count, [4..6] sum v ([0..2] stay 0)
+    unsigned long long part[kSlots][kMaxDust][3];  // Eq.(1) sums, per slot (block index mod kSlots)
     unsigned long long n_exit[kSlots];     // exits, per slot
     unsigned long long n_coll[kSlots];     // collisions, per slot
-    unsigned long long n_lost[kSlots];     // lost-list segment lengths
+    unsigned int ticket_slot[kSlots];      // tail blocks of the slot that have finished
+    unsigned int lost_seg[kSlots];         // lost-list segment lengths (single system)
     double Q[kMaxDust];                    // charge, e
     double last[kMaxDust][16];             // [0] Q^n, [1..12] F parts (SI), [13] absorbed count
     double sums[kMaxDust][16];             // running sums over recorded steps
@@ -46,7 +48,9 @@ struct Ctl {
     long long nrec;                        // recorded steps
     long long last_exit, last_coll;
     int status;
-    int pad[7];
+    unsigned int ticket;                   // slots of the tail whose blocks have all finished
+    unsigned int lost_ticket;              // reinjection blocks that have finished
+    int pad[5];
 };
 
 // ---------------------------------------------------------------------------

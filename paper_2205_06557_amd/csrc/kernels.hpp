@@ -5,14 +5,17 @@
 //       of each grain, homogeneous drive; plus the per-grain sum of Eq. (1)
 //       over all ions, reduced per block and added to int64 fixed-point
 //       accumulators.
-//   push_kernel<T>      kick, charge exchange, drift, absorption test against
-//       every grain along the drift segment, exit test, per-ion event byte;
-//       lost ions are appended to a list.
-//   reinject_kernel<T>  new boundary position and velocity for every listed
+//   step_tail_kernel<T, FIX>  the rest of the step, per ion: acceleration
+//       from the symmetric pair sum's totals plus the grain terms and the
+//       Eq. (1) summands (FIX), kick, charge exchange, drift, absorption test
+//       against every grain along the drift segment, exit test, per-ion
+//       event byte, list of lost ions; the system's last block to finish
+//       updates the charges (the three
+//       charging models of Section 2), assembles the four force parts of
+//       Eqs. (1)-(4) in SI, records the step, keeps the time averages,
+//       clears the accumulators and advances the step counter.
+//   reinject_kernel<T>  new boundary position and velocity of every listed
 //       ion (Appendix B).
-//   finalize_kernel     one wave: charge update (the three charging models of
-//       Section 2), the four force parts of Eqs. (1)-(4) in SI, recording,
-//       time averages, clearing of the accumulators, step counter.
 //   init_kernel<T>      initial uniform positions and shifted-Maxwellian
 //       velocities.
 //   conf_grid_kernel<T> potential of the plasma outside the domain on the
@@ -49,6 +52,7 @@ struct ConfField {
 __host__ __device__ inline void conf_field(const ConfField& f, double x, double y, double z,
                                            double& ex, double& ey, double& ez)
 {
+#pragma clang fp contract(off)
     const double* c = f.c;
     const double u = (x * x + y * y) * f.iu, v = z * z * f.iv;
     const double u2 = u * u, v2 = v * v;
@@ -100,7 +104,13 @@ struct FinalArgs {
     double c_coll;                  // N per (dimensionless velocity sum)
     double c_ext;                   // N per e (e * E_SI)
     double eout[kMaxDust][3];       // N per e: e * E_out(r_d) of the confinement field, or 0
+    double* hist;                   // per-step records [hist_cap][nd][kHistWords], or null
+    long long hist_start, hist_cap; // steps hist_start .. hist_start + hist_cap - 1 are recorded
 };
+
+// Words of one per-step record: Q^n (e), the twelve force components (SI),
+// the absorbed count.
+constexpr int kHistWords = 14;
 
 // ---------------------------------------------------------------------------
 // End of a block of 256 target ions: adds (when epi) the grain terms in FP64
@@ -153,7 +163,7 @@ __device__ __forceinline__ void pair_epilogue(float xi, float yi, float zi, int 
             const int d = t / 3, c = t % 3;
             double s = 0.0;
             for (int w = 0; w < BLOCK / 64; ++w) s += red[w][d][c];
-            atomicAdd(&ctl->acc[d][c], to_fixed(s, kForceScale, &ctl->status));
+            atomicAdd(&ctl->part[blockIdx.x % kSlots][d][c], to_fixed(s, kForceScale, &ctl->status));
         }
     }
     __syncthreads();
@@ -338,7 +348,7 @@ __global__ __launch_bounds__(BLOCK) void pair_forces_f64(const double* __restric
         const int d = t / 3, c = t % 3;
         double s = 0.0;
         for (int w = 0; w < BLOCK / 64; ++w) s += red[w][d][c];
-        atomicAdd(&ctl->acc[d][c], to_fixed(s, kForceScale, &ctl->status));
+        atomicAdd(&ctl->part[blockIdx.x % kSlots][d][c], to_fixed(s, kForceScale, &ctl->status));
     }
 }
 
@@ -357,7 +367,10 @@ __device__ inline double inflow(double m, double s)
 // Flux-weighted normal speed on a face: the v >= 0 whose flux tail
 // int_v^inf v' phi(v') dv' equals uu times the total inflow.  Newton on the
 // tail (slope -v phi(v)) inside a shrinking bracket, bisection when a Newton
-// step leaves it; stops when a step is below 1e-13 s.
+// step would not land strictly inside it; stops when a step is below
+// 1e-13 s, or when the tail equals the goal to within the rounding of its
+// own evaluation, 8 ulp of the magnitudes of its terms (where the flux
+// density is tiny the root is resolved no further than that).
 __device__ double flux_speed(double uu, double m, double s)
 {
     const double goal = uu * inflow(m, s);
@@ -366,15 +379,15 @@ __device__ double flux_speed(double uu, double m, double s)
     double v = fmax(m, 0.0) + s;
     for (int it = 0; it < 400; ++it) {
         const double t = (v - m) / s;
-        const double tail = m * 0.5 * erfc(t * 0.70710678118654752440) + s * npdf(t);
-        const double g = tail - goal;
+        const double t1 = m * 0.5 * erfc(t * 0.70710678118654752440), t2 = s * npdf(t);
+        const double g = (t1 + t2) - goal;
+        if (fabs(g) <= 8.0 * 2.220446049250313e-16 * (fabs(t1) + t2)) break;
         if (g > 0.0) lo = v; else hi = v;
         const double slope = -v * npdf(t) / s;
         double nv = 0.5 * (lo + hi);
         if (slope < 0.0) {
-            // a converged step lands on the bracket end it just moved: keep it
             const double cand = v - g / slope;
-            if (cand >= lo && cand <= hi) nv = cand;
+            if (cand > lo && cand < hi) nv = cand;
         }
         const bool done = fabs(nv - v) <= 1e-13 * s;
         v = nv;
@@ -406,27 +419,27 @@ __device__ inline double fd_A(double x, double ufd, double sig)
 __device__ double fd_speed(double uu, double ufd, double sig, bool top)
 {
     const double k = 0.70710678118654752440;
-    auto tail = [&](double v, double& slope) {
-        if (top) {
-            const double A = fd_A(-v, ufd, sig);
-            slope = -v * A / ufd;
-            return (ufd - v) * A + sig * npdf(v / sig) - ufd * 0.5 * erfc(v / sig * k);
-        }
-        const double A = fd_A(v, ufd, sig);
+    // tail at v, its slope and the magnitude of its terms (rounding scale)
+    auto tail = [&](double v, double& slope, double& mag) {
+        const double A = fd_A(top ? -v : v, ufd, sig);
         slope = -v * A / ufd;
-        return (v + ufd) * A + sig * npdf(v / sig) + ufd * 0.5 * erfc(v / sig * k);
+        const double t1 = (top ? ufd - v : v + ufd) * A, t2 = sig * npdf(v / sig);
+        const double t3 = ufd * 0.5 * erfc(v / sig * k);
+        mag = fabs(t1) + t2 + t3;
+        return top ? (t1 + t2) - t3 : (t1 + t2) + t3;
     };
-    double slope;
-    const double goal = uu * tail(0.0, slope);
+    double slope, mag;
+    const double goal = uu * tail(0.0, slope, mag);
     double lo = 0.0, hi = 40.0 * sig + (top ? 0.0 : 50.0 * ufd);
     double v = top ? sig : ufd + sig;
     for (int it = 0; it < 400; ++it) {
-        const double g = tail(v, slope) - goal;
+        const double g = tail(v, slope, mag) - goal;
+        if (fabs(g) <= 8.0 * 2.220446049250313e-16 * mag) break;   // as flux_speed
         if (g > 0.0) lo = v; else hi = v;
         double nv = 0.5 * (lo + hi);
         if (slope < 0.0) {
             const double cand = v - g / slope;
-            if (cand >= lo && cand <= hi) nv = cand;
+            if (cand > lo && cand < hi) nv = cand;
         }
         const bool done = fabs(nv - v) <= 1e-13 * sig;
         v = nv;
@@ -475,31 +488,29 @@ __device__ void reinject(const PushArgs& p, uint64_t ion, uint64_t n, double o[6
 }
 
 // ---------------------------------------------------------------------------
-// Push of one ion: kick with the acceleration (the sum of `nsplit` partial
-// planes `sstride` apart), charge exchange, drift, absorption test against
-// every grain along the drift segment, exit test.  Planes use the system's
-// local ion index.  Absorbed ions add to the grain's count and momentum.
+// The per-ion tail of a step, one kernel: acceleration (for the symmetric
+// pair sum: its fixed-point totals plus the grain, drive and confinement
+// terms, and the ion's share of the Eq. (1) sums), kick, charge exchange,
+// drift, absorption test against every grain along the drift segment, exit
+// test, reinjection of a lost ion on the boundary (Appendix B) by the thread
+// that lost it, and, in the last block of the system to finish, the charge
+// update and force assembly.
+
+// Kick, charge exchange and drift of one ion from x with velocity v and
+// acceleration a; absorption (the earliest grain met along the drift
+// segment, ties to the lower index) and exit tests.  Returns the new x, v in
+// y, w; absorbed ions add to the grain's count and momentum.
 template <typename T>
-__device__ __forceinline__ void push_ion(T* __restrict__ X, T* __restrict__ Y, T* __restrict__ Z,
-                                         T* __restrict__ VX, T* __restrict__ VY,
-                                         T* __restrict__ VZ, const T* __restrict__ AX,
-                                         const T* __restrict__ AY, const T* __restrict__ AZ,
-                                         long long sstride, int nsplit, int i, uint64_t n,
-                                         const PushArgs& p, const DustSet& ds,
-                                         Ctl* __restrict__ ctl, uint8_t& code, bool& coll,
-                                         bool& lost)
+__device__ __forceinline__ void push_core(const T x[3], const T v[3], const T a[3], int i, uint64_t n,
+                                          const PushArgs& p, const DustSet& ds, Ctl* __restrict__ ctl,
+                                          T y[3], T w[3], uint8_t& code, bool& coll, bool& lost)
 {
+#pragma clang fp contract(off)      // the same rounding in every kernel that inlines it
     const T dt = (T)p.dt;
-    T ax = AX[i], ay = AY[i], az = AZ[i];
-    for (int k = 1; k < nsplit; ++k) {
-        ax += AX[i + k * sstride];
-        ay += AY[i + k * sstride];
-        az += AZ[i + k * sstride];
-    }
-    const T x0 = X[i], x1 = Y[i], x2 = Z[i];
-    T v0 = VX[i] + dt * ax;
-    T v1 = VY[i] + dt * ay;
-    T v2 = VZ[i] + dt * az;
+    // kick and drift with one rounding each (fused multiply-add)
+    T v0 = fma(dt, a[0], v[0]);
+    T v1 = fma(dt, a[1], v[1]);
+    T v2 = fma(dt, a[2], v[2]);
     if (p.Tc != 0) {
         const U64x4 r = philox((uint64_t)i, n, kColl, 0, p.k0, p.k1);
         if (r.w[0] < p.Tc) {
@@ -513,17 +524,17 @@ __device__ __forceinline__ void push_ion(T* __restrict__ X, T* __restrict__ Y, T
             coll = true;
         }
     }
-    const T y0 = x0 + dt * v0, y1 = x1 + dt * v1, y2 = x2 + dt * v2;
+    const T y0 = fma(dt, v0, x[0]), y1 = fma(dt, v1, x[1]), y2 = fma(dt, v2, x[2]);
     // Absorption: does the drift segment x -> y meet a grain?  FP64 on
     // the stored values; the earliest entry wins, ties to the lower index.
     int hit = -1;
     double tbest = 2.0;
-    const double D0 = (double)y0 - (double)x0, D1 = (double)y1 - (double)x1,
-                 D2 = (double)y2 - (double)x2;
+    const double D0 = (double)y0 - (double)x[0], D1 = (double)y1 - (double)x[1],
+                 D2 = (double)y2 - (double)x[2];
     const double DD = D0 * D0 + D1 * D1 + D2 * D2;
     for (int d = 0; d < ds.nd; ++d) {
-        const double s0 = (double)x0 - ds.pos[d][0], s1 = (double)x1 - ds.pos[d][1],
-                     s2 = (double)x2 - ds.pos[d][2];
+        const double s0 = (double)x[0] - ds.pos[d][0], s1 = (double)x[1] - ds.pos[d][1],
+                     s2 = (double)x[2] - ds.pos[d][2];
         const double a2 = ds.rad2[d];
         const double ss = s0 * s0 + s1 * s1 + s2 * s2;
         const double sD = s0 * D0 + s1 * D1 + s2 * D2;
@@ -566,114 +577,142 @@ __device__ __forceinline__ void push_ion(T* __restrict__ X, T* __restrict__ Y, T
             lost = true;
         }
     }
-    // lost ions are overwritten by the reinjection kernel
-    X[i] = y0; Y[i] = y1; Z[i] = y2;
-    VX[i] = v0; VY[i] = v1; VZ[i] = v2;
+    y[0] = y0; y[1] = y1; y[2] = y2;
+    w[0] = v0; w[1] = v1; w[2] = v2;
 }
 
-// Capacity of one lost-list segment for a push grid of nblk blocks of 256
-// ions: the blocks of a slot hold at most this many ions, so no segment can
-// overflow.
-__host__ __device__ inline long long seg_cap(int nblk)
+// Acceleration of ion i from the symmetric pair sum's fixed-point totals
+// fix[c * fstride + i] (cleared here), the homogeneous drive, the
+// confinement field and the bare Coulomb pull of every grain (FP32 terms of
+// FP64 differences, summed in FP64).  When `eq1` is set the ion's Eq. (1)
+// summands (1 + rho) e^-rho / rho^3 (r_d - x_i), FP32 terms, are reduced over
+// the wave in FP64 into red[wave][d][c] (zero for a padding slot).  All lanes
+// of the wave must call it.  Floating-point contraction is off here (the only
+// fused operations are the written fmaf), so that every kernel that inlines
+// it rounds alike: a system in a batch reproduces the same system run alone.
+__device__ __forceinline__ void accel_from_fixed(const float x[3], bool live, int i,
+                                                 unsigned long long* __restrict__ fix, long long fstride,
+                                                 const PairArgs& pa, const DustSet& ds, const double* Kd,
+                                                 float a[3], double (*red)[kMaxDust][3])
 {
-    return (long long)((nblk + kSlots - 1) / kSlots) * 256;
+#pragma clang fp contract(off)
+    double g[3];
+    for (int c = 0; c < 3; ++c) {
+        unsigned long long* q = &fix[c * fstride + i];
+        g[c] = live ? pa.Cd * from_fixed(*q, pa.sym_scale) : 0.0;
+        *q = 0ull;
+    }
+    g[2] += pa.Ez;
+    if (pa.cf.on) {
+        double ex, ey, ez;
+        conf_field(pa.cf, x[0], x[1], x[2], ex, ey, ez);
+        g[0] += ex; g[1] += ey; g[2] += ez;
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const float kNegLog2e = -1.4426950408889634f;
+    for (int d = 0; d < ds.nd; ++d) {
+        const float rx = (float)((double)x[0] - ds.pos[d][0]);
+        const float ry = (float)((double)x[1] - ds.pos[d][1]);
+        const float rz = (float)((double)x[2] - ds.pos[d][2]);
+        const float r2 = fmaf(rx, rx, fmaf(ry, ry, rz * rz));
+        const float ri = __builtin_amdgcn_rsqf(r2);
+        const float ir3 = ri * ri * ri;
+        const float kq = (float)Kd[d] * ir3;                          // bare Coulomb on the ion
+        g[0] += (double)(kq * rx); g[1] += (double)(kq * ry); g[2] += (double)(kq * rz);
+        // Eq. (1) summand, the grain's side: -(1 + rho) e^-rho / rho^3 (x_i - r_d)
+        const float rho = r2 * ri;
+        const float e = __builtin_amdgcn_exp2f(rho * kNegLog2e);
+        const float f = live ? -(fmaf(rho, e, e) * ir3) : 0.0f;
+        const double fx = wave_sum((double)(f * rx)), fy = wave_sum((double)(f * ry)),
+                     fz = wave_sum((double)(f * rz));
+        if (lane == 0) {
+            red[wv][d][0] = fx;
+            red[wv][d][1] = fy;
+            red[wv][d][2] = fz;
+        }
+    }
+    a[0] = (float)g[0]; a[1] = (float)g[1]; a[2] = (float)g[2];
 }
 
-// Wave totals of exits and collisions into the system's counters (slot of
-// this block), and a place in the slot's segment of the lost list (segment
-// lengths in seg_len[kSlots], capacity cap) for every lane with `lost` set.
-// All lanes of the wave must call it.  Returns the lane's list index (valid
-// if `lost`).
-__device__ __forceinline__ long long wave_tally(Ctl* __restrict__ ctl, uint8_t code, bool coll,
-                                                bool lost, unsigned long long* seg_len, long long cap)
+// Ions lost in a step (absorbed or exited), as (system, ion) pairs, for the
+// reinjection kernel.  The list is cut into kSlots segments of `cap` entries;
+// block b of the tail appends its lost ions to segment b mod kSlots
+// (seg[slot] counts them), so that blocks do not all add to one counter.
+struct LostList {
+    unsigned int* seg;       // [kSlots] segment lengths
+    unsigned int* ticket;    // reinjection blocks that have finished
+    int2* item;              // [kSlots * cap]
+    long long cap;
+};
+
+// Segment capacity for a tail grid of nblk blocks of 256 ions: the blocks of
+// one slot hold at most this many ions, so no segment can overflow.
+__host__ __device__ inline long long lost_cap(long long nblk)
 {
-    const int slot = blockIdx.x % kSlots;
-    const unsigned long long ex = __ballot(code == kEvExit);
-    const unsigned long long cl = __ballot(coll);
-    const unsigned long long ls = __ballot(lost);
+    return (nblk + kSlots - 1) / kSlots * 256;
+}
+
+// Wave64 sum of an unsigned 64-bit integer (two's-complement wrap, so the
+// fixed-point words add exactly).
+__device__ inline unsigned long long wave_sum_u64(unsigned long long v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+// Charge update (the three charging models of Section 2), the four force
+// parts of Eqs. (1)-(4) in SI, recording of step n (the charge Q^n used in
+// the step and the forces of the step), running sums over n >= n_discard,
+// optional history, counters cleared, step counter advanced.  Run by one
+// wave (lane d handles grain d; lane l also sums slot l of the per-slot
+// counters), after every contribution to the counters is visible; no block
+// barrier, so the block's other waves may have left.
+__device__ void finalize_wave(const FinalArgs& f, const DustSet& ds, Ctl* __restrict__ ctl)
+{
     const int lane = threadIdx.x & 63;
-    unsigned long long base = 0;
-    if (lane == 0) {
-        if (ex) atomicAdd(&ctl->n_exit[slot], (unsigned long long)__popcll(ex));
-        if (cl) atomicAdd(&ctl->n_coll[slot], (unsigned long long)__popcll(cl));
-        if (ls) base = atomicAdd(&seg_len[slot], (unsigned long long)__popcll(ls));
-    }
-    base = __shfl(base, 0, 64);
-    return slot * cap + (long long)base + __popcll(ls & ((1ull << lane) - 1ull));
-}
-
-// Push of one system: one ion per thread.
-template <typename T>
-__global__ __launch_bounds__(256) void push_kernel(T* __restrict__ xs, T* __restrict__ vs,
-                                                   const T* __restrict__ as,
-                                                   uint8_t* __restrict__ ev,
-                                                   int* __restrict__ lost_list, PushArgs p,
-                                                   DustSet ds, Ctl* __restrict__ ctl, int nsplit)
-{
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    const int Npad = p.Npad;
-    const uint64_t n = (uint64_t)ctl->step;
-    bool coll = false, lost = false;
-    uint8_t code = kEvNone;
-    if (i < p.N) {
-        push_ion<T>(xs, xs + Npad, xs + 2 * Npad, vs, vs + Npad, vs + 2 * Npad, as, as + Npad,
-                    as + 2 * Npad, 3LL * Npad, nsplit, i, n, p, ds, ctl, code, coll, lost);
-        ev[i] = code | (coll ? kEvCollBit : 0);
-    }
-    const long long at = wave_tally(ctl, code, coll, lost, ctl->n_lost, seg_cap(gridDim.x));
-    if (lost) lost_list[at] = i;
-}
-
-// New boundary position and velocity of listed ion i (Appendix B).
-template <typename T>
-__device__ __forceinline__ void reinject_ion(T* __restrict__ X, T* __restrict__ Y,
-                                             T* __restrict__ Z, T* __restrict__ VX,
-                                             T* __restrict__ VY, T* __restrict__ VZ, int i,
-                                             uint64_t n, const PushArgs& p)
-{
-    double o[6];
-    reinject(p, (uint64_t)i, n, o);
-    X[i] = (T)o[0]; Y[i] = (T)o[1]; Z[i] = (T)o[2];
-    VX[i] = (T)o[3]; VY[i] = (T)o[4]; VZ[i] = (T)o[5];
-}
-
-// Reinjection of the ions the push listed.  Block b walks segment
-// b mod kSlots of the list (length left by the push in n_lost); the grid is
-// a multiple of kSlots.  cap: segment capacity of the push grid.
-template <typename T>
-__global__ __launch_bounds__(64) void reinject_kernel(T* __restrict__ xs, T* __restrict__ vs,
-                                                     const int* __restrict__ lost_list, PushArgs p,
-                                                     long long cap, Ctl* __restrict__ ctl)
-{
-    const int slot = blockIdx.x % kSlots, part = blockIdx.x / kSlots, parts = gridDim.x / kSlots;
-    const long long cnt = (long long)ctl->n_lost[slot];
-    const uint64_t n = (uint64_t)ctl->step;
-    const int Npad = p.Npad;
-    const int* seg = lost_list + slot * cap;
-    for (long long k = part * 64 + threadIdx.x; k < cnt; k += (long long)parts * 64)
-        reinject_ion<T>(xs, xs + Npad, xs + 2 * Npad, vs, vs + Npad, vs + 2 * Npad, seg[k], n, p);
-}
-
-// ---------------------------------------------------------------------------
-// Finalize of one system by one wave (lane d handles grain d): charge update,
-// the four force parts in SI, recording, running sums, counters cleared,
-// step counter advanced.
-__device__ __forceinline__ void finalize_sys(const FinalArgs& f, const DustSet& ds,
-                                             Ctl* __restrict__ ctl, double* Qs)
-{
-    const int d = threadIdx.x;
-    if (d < f.nd) Qs[d] = ctl->Q[d];
-    __syncthreads();
+    const int d = lane;
     const long long n = ctl->step;
+    const double Qn = d < f.nd ? ctl->Q[d] : 0.0;
+    // Eq. (1) sums: slot `lane` of every grain's three words, summed over the
+    // wave (integers, so the order does not matter), cleared for the next step
+    double S[3] = {0.0, 0.0, 0.0};
+    for (int g = 0; g < f.nd; ++g)
+        for (int c = 0; c < 3; ++c) {
+            unsigned long long* q = &ctl->part[lane][g][c];
+            const unsigned long long v = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            *q = 0ull;
+            const unsigned long long t =
+                wave_sum_u64(v) + __hip_atomic_load(&ctl->acc[g][c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (g == d) S[c] = from_fixed(t, kForceScale);
+        }
+    // event counters: one slot per lane
+    const double ne = wave_sum((double)__hip_atomic_load(&ctl->n_exit[lane], __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT));
+    const double nc = wave_sum((double)__hip_atomic_load(&ctl->n_coll[lane], __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT));
+    ctl->n_exit[lane] = 0ull;
+    ctl->n_coll[lane] = 0ull;
+    ctl->ticket_slot[lane] = 0u;
+    // the other grains' charges Q^n for Eq. (2)
+    double px = 0.0, py = 0.0, pz = 0.0;
+    for (int q = 0; q < f.nd; ++q) {
+        const double Qq = __shfl(Qn, q, 64);
+        if (q == d || d >= f.nd) continue;
+        const double rx = ds.pos[d][0] - ds.pos[q][0], ry = ds.pos[d][1] - ds.pos[q][1],
+                     rz = ds.pos[d][2] - ds.pos[q][2];
+        const double r2 = rx * rx + ry * ry + rz * rz;
+        const double k = Qq / (r2 * sqrt(r2));
+        px += k * rx; py += k * ry; pz += k * rz;
+    }
     if (d < f.nd) {
-        const double Qn = Qs[d];
-        const double S0 = from_fixed(ctl->acc[d][0], kForceScale);
-        const double S1 = from_fixed(ctl->acc[d][1], kForceScale);
-        const double S2 = from_fixed(ctl->acc[d][2], kForceScale);
-        const double cntd = (double)(long long)ctl->acc[d][3];
-        const double P0 = from_fixed(ctl->acc[d][4], kMomScale);
-        const double P1 = from_fixed(ctl->acc[d][5], kMomScale);
-        const double P2 = from_fixed(ctl->acc[d][6], kMomScale);
+        unsigned long long acc[4];
+        for (int c = 0; c < 4; ++c)
+            acc[c] = __hip_atomic_load(&ctl->acc[d][3 + c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const double cntd = (double)(long long)acc[0];
+        const double P0 = from_fixed(acc[1], kMomScale);
+        const double P1 = from_fixed(acc[2], kMomScale);
+        const double P2 = from_fixed(acc[3], kMomScale);
         for (int c = 0; c < 8; ++c) ctl->acc[d][c] = 0ull;
 
         // charge update
@@ -694,18 +733,9 @@ __device__ __forceinline__ void finalize_sys(const FinalArgs& f, const DustSet& 
         // forces, SI
         double F[12];
         const double co = f.c_orbit * Qn;
-        F[0] = co * S0 + Qn * f.eout[d][0];
-        F[1] = co * S1 + Qn * f.eout[d][1];
-        F[2] = co * S2 + Qn * f.eout[d][2];
-        double px = 0.0, py = 0.0, pz = 0.0;
-        for (int q = 0; q < f.nd; ++q) {
-            if (q == d) continue;
-            const double rx = ds.pos[d][0] - ds.pos[q][0], ry = ds.pos[d][1] - ds.pos[q][1],
-                         rz = ds.pos[d][2] - ds.pos[q][2];
-            const double r2 = rx * rx + ry * ry + rz * rz;
-            const double k = Qs[q] / (r2 * sqrt(r2));
-            px += k * rx; py += k * ry; pz += k * rz;
-        }
+        F[0] = co * S[0] + Qn * f.eout[d][0];
+        F[1] = co * S[1] + Qn * f.eout[d][1];
+        F[2] = co * S[2] + Qn * f.eout[d][2];
         const double cd = f.c_dd * Qn;
         F[3] = cd * px; F[4] = cd * py; F[5] = cd * pz;
         F[6] = f.c_coll * P0; F[7] = f.c_coll * P1; F[8] = f.c_coll * P2;
@@ -722,31 +752,235 @@ __device__ __forceinline__ void finalize_sys(const FinalArgs& f, const DustSet& 
             ctl->sums[d][0] += Qn;
             for (int c = 0; c < 12; ++c) ctl->sums[d][1 + c] += F[c];
         }
+        if (f.hist && n >= f.hist_start && n < f.hist_start + f.hist_cap) {
+            double* h = f.hist + ((n - f.hist_start) * f.nd + d) * kHistWords;
+            h[0] = Qn;
+            for (int c = 0; c < 12; ++c) h[1 + c] = F[c];
+            h[13] = cntd;
+        }
         ctl->Q[d] = Qnew;
         if (bad) atomicOr(&ctl->status, kStNaN);
     }
-    __syncthreads();
-    // event counters: one slot per lane (blockDim.x == kSlots == 64)
-    const double ne = wave_sum((double)ctl->n_exit[d]);
-    const double nc = wave_sum((double)ctl->n_coll[d]);
-    ctl->n_exit[d] = 0ull;
-    ctl->n_coll[d] = 0ull;
-    ctl->n_lost[d] = 0ull;
-    if (d == 0) {
+    if (lane == 0) {
         ctl->last_exit = (long long)ne;
         ctl->last_coll = (long long)nc;
         if (n >= f.n_discard) ctl->nrec += 1;
+        ctl->ticket = 0u;
         ctl->step = n + 1;
     }
 }
 
-__global__ __launch_bounds__(64) void finalize_kernel(FinalArgs f, DustSet ds,
-                                                      Ctl* __restrict__ ctl)
+// The tail of one block of 256 ions of one system (planes X.. of the
+// system, local ion index i = i0 + threadIdx.x): FIX selects the symmetric
+// pair sum (acceleration assembled here from fix, written to AX..) over
+// precomputed acceleration planes (AX.. plus nsplit - 1 partial planes
+// sstride apart).  nblk: the system's number of tail blocks.  After the
+// block's counters are added, the last block of the system to finish (a
+// ticket counter in the control block) runs finalize_wave.
+template <typename T, bool FIX, bool INL = false>
+__device__ __forceinline__ void tail_block(T* __restrict__ X, T* __restrict__ Y, T* __restrict__ Z,
+                                           T* __restrict__ VX, T* __restrict__ VY, T* __restrict__ VZ,
+                                           T* __restrict__ AX, T* __restrict__ AY, T* __restrict__ AZ,
+                                           long long sstride, int nsplit, unsigned long long* __restrict__ fix,
+                                           long long fstride, uint8_t* __restrict__ ev, int i0, int nblk,
+                                           const PairArgs& pa, const PushArgs& pu, const DustSet& ds,
+                                           const FinalArgs& fa, Ctl* __restrict__ ctl, int sys,
+                                           LostList lost_list)
 {
-    __shared__ double Qs[kMaxDust];
-    finalize_sys(f, ds, ctl, Qs);
+    __shared__ double red[4][kMaxDust][3];
+    __shared__ double Kd[kMaxDust];
+    __shared__ unsigned int wtally[3][4];
+    __shared__ unsigned int lbase;
+    const int i = i0 + threadIdx.x;
+    const bool live = i < pu.N;
+    const uint64_t n = (uint64_t)ctl->step;
+    if (FIX) {
+        if (threadIdx.x < ds.nd) Kd[threadIdx.x] = pa.Kq * ctl->Q[threadIdx.x];
+        __syncthreads();
+    }
+    T x[3], v[3], a[3];
+    x[0] = X[i]; x[1] = Y[i]; x[2] = Z[i];
+    v[0] = VX[i]; v[1] = VY[i]; v[2] = VZ[i];   // padding slots hold zeros
+    if (FIX) {
+        float xf[3] = {(float)x[0], (float)x[1], (float)x[2]}, af[3];
+        accel_from_fixed(xf, live, i, fix, fstride, pa, ds, Kd, af, red);
+        a[0] = af[0]; a[1] = af[1]; a[2] = af[2];
+        if (live) {
+            AX[i] = a[0]; AY[i] = a[1]; AZ[i] = a[2];
+        }
+    } else {
+        a[0] = AX[i]; a[1] = AY[i]; a[2] = AZ[i];
+        for (int k = 1; k < nsplit; ++k) {
+            a[0] += AX[i + k * sstride];
+            a[1] += AY[i + k * sstride];
+            a[2] += AZ[i + k * sstride];
+        }
+    }
+    bool coll = false, lost = false;
+    uint8_t code = kEvNone;
+    if (live) {
+        T y[3], w[3];
+        push_core<T>(x, v, a, i, n, pu, ds, ctl, y, w, code, coll, lost);
+        if (INL && lost) {          // new boundary ion (Appendix B), here
+            double o[6];
+            reinject(pu, (uint64_t)i, n, o);
+            for (int c = 0; c < 3; ++c) {
+                y[c] = (T)o[c];
+                w[c] = (T)o[3 + c];
+            }
+        }
+        // else a lost ion is overwritten by the reinjection kernel
+        X[i] = y[0]; Y[i] = y[1]; Z[i] = y[2];
+        VX[i] = w[0]; VY[i] = w[1]; VZ[i] = w[2];
+        ev[i] = code | (coll ? kEvCollBit : 0);
+    }
+    // Block totals: exits, collisions and lost ions per wave, then one
+    // atomic per counter and block, on the block's slot.
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const unsigned long long mex = __ballot(code == kEvExit), mcl = __ballot(coll), mls = __ballot(lost);
+    if (lane == 0) {
+        wtally[0][wv] = (unsigned int)__popcll(mex);
+        wtally[1][wv] = (unsigned int)__popcll(mcl);
+        wtally[2][wv] = (unsigned int)__popcll(mls);
+    }
+    __syncthreads();
+    const int lblk = i0 / 256;                   // the block's index within its system
+    const int slot = lblk % kSlots;
+    if (threadIdx.x == 0) {
+        const unsigned int ne = wtally[0][0] + wtally[0][1] + wtally[0][2] + wtally[0][3];
+        const unsigned int nc = wtally[1][0] + wtally[1][1] + wtally[1][2] + wtally[1][3];
+        const unsigned int nl = wtally[2][0] + wtally[2][1] + wtally[2][2] + wtally[2][3];
+        if (ne) atomicAdd(&ctl->n_exit[slot], (unsigned long long)ne);
+        if (nc) atomicAdd(&ctl->n_coll[slot], (unsigned long long)nc);
+        lbase = (nl && !INL) ? atomicAdd(&lost_list.seg[blockIdx.x % kSlots], nl) : 0u;
+    }
+    if (FIX && ds.nd > 0) {
+        for (int t = threadIdx.x; t < ds.nd * 3; t += blockDim.x) {
+            const int d = t / 3, c = t % 3;
+            const double sum = ((red[0][d][c] + red[1][d][c]) + red[2][d][c]) + red[3][d][c];
+            atomicAdd(&ctl->part[slot][d][c], to_fixed(sum, kForceScale, &ctl->status));
+        }
+    }
+    __syncthreads();
+    if (lost && !INL) {
+        unsigned int r = lbase + (unsigned int)__popcll(mls & ((1ull << lane) - 1ull));
+        for (int k = 0; k < wv; ++k) r += wtally[2][k];
+        lost_list.item[(long long)(blockIdx.x % kSlots) * lost_list.cap + r] = make_int2(sys, i);
+    }
+    // The last block of the system to get here finalizes the step.  Every
+    // contribution to the counters is a device-scope atomic, performed where
+    // all blocks see it; each wave waits until its own have completed before
+    // the block takes its ticket (also an atomic).  With more blocks than
+    // slots, tickets are counted per slot and the block that completes a slot
+    // adds to the system's ticket, so that no counter takes one atomic per
+    // block.  When the system's ticket is complete every contribution is in
+    // place; only that block then fences (one cache invalidation per step, not
+    // one per wave).
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (wv != 0) return;            // the ticket and the finalize need one wave
+    int is_last = 0;
+    if (lane == 0) {
+        if (nblk <= kSlots) {
+            is_last = atomicAdd(&ctl->ticket, 1u) == (unsigned int)(nblk - 1);
+        } else {
+            const int per_slot = nblk / kSlots + (slot < nblk % kSlots ? 1 : 0);
+            if (atomicAdd(&ctl->ticket_slot[slot], 1u) == (unsigned int)(per_slot - 1))
+                is_last = atomicAdd(&ctl->ticket, 1u) == (unsigned int)(kSlots - 1);
+        }
+    }
+    if (__shfl(is_last, 0, 64)) {
+        __threadfence();
+        finalize_wave(fa, ds, ctl);
+    }
 }
 
+// The tail of one system: block b handles ions [256 b, 256 b + 256).  INL:
+// lost ions are reinjected by the thread that lost them (small systems, where
+// a step is a chain of short kernels and a separate reinjection launch would
+// lengthen it; the FP64 sampling then sets the kernel's register budget),
+// else listed for reinject_kernel.
+template <typename T, bool FIX, bool INL>
+__global__ __launch_bounds__(256) void step_tail_kernel(T* __restrict__ xs, T* __restrict__ vs,
+                                                        T* __restrict__ as, unsigned long long* __restrict__ fix,
+                                                        uint8_t* __restrict__ ev, int nsplit, PairArgs pa,
+                                                        PushArgs pu, DustSet ds, FinalArgs fa,
+                                                        Ctl* __restrict__ ctl, LostList lost_list)
+{
+    const long long P = pu.Npad;
+    tail_block<T, FIX, INL>(xs, xs + P, xs + 2 * P, vs, vs + P, vs + 2 * P, as, as + P, as + 2 * P, 3 * P,
+                            nsplit, fix, P, ev, blockIdx.x * 256, gridDim.x, pa, pu, ds, fa, ctl, 0, lost_list);
+}
+
+// Reinjection (Appendix B) of the ions the step's tail listed: a grid-stride
+// walk of the list; the new position and velocity of ion i of system s come
+// from the blocks (i, n, REINJ, 0/1) of that system's stream, n the step
+// just finalized.  The last block to finish empties the list for the next
+// step.  sysp(s) gives the system's planes and constants.
+template <typename T, typename Sys>
+__device__ __forceinline__ void reinject_list(LostList L, const Sys& sysp)
+{
+    static_assert(kSlots == 64, "one segment per lane");
+    __shared__ unsigned int pre[kSlots + 1];
+    __shared__ int last;
+    if (threadIdx.x < kSlots) {        // segment offsets of the listed ions: a wave scan
+        const unsigned int len = L.seg[threadIdx.x];
+        unsigned int inc = len;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned int u = __shfl_up(inc, o, 64);
+            if ((int)threadIdx.x >= o) inc += u;
+        }
+        pre[threadIdx.x] = inc - len;
+        if (threadIdx.x == kSlots - 1) pre[kSlots] = inc;
+    }
+    __syncthreads();
+    const unsigned int cnt = pre[kSlots];
+    for (unsigned int k = blockIdx.x * blockDim.x + threadIdx.x; k < cnt; k += gridDim.x * blockDim.x) {
+        int lo = 0, hi = kSlots;       // the segment holding entry k: pre[lo] <= k < pre[lo + 1]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (pre[mid] <= k) lo = mid; else hi = mid;
+        }
+        const int2 e = L.item[(long long)lo * L.cap + (k - pre[lo])];
+        T *X, *V;
+        const PushArgs* pu;
+        const Ctl* ctl;
+        long long P;
+        sysp(e.x, X, V, pu, ctl, P);
+        double o[6];
+        reinject(*pu, (uint64_t)e.y, (uint64_t)(ctl->step - 1), o);
+        X[e.y] = (T)o[0]; X[P + e.y] = (T)o[1]; X[2 * P + e.y] = (T)o[2];
+        V[e.y] = (T)o[3]; V[P + e.y] = (T)o[4]; V[2 * P + e.y] = (T)o[5];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(L.ticket, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (last && threadIdx.x < kSlots) {     // every block has read the lengths
+        L.seg[threadIdx.x] = 0u;
+        if (threadIdx.x == 0) *L.ticket = 0u;
+    }
+}
+
+template <typename T>
+struct OneSystem {
+    T* xs;
+    T* vs;
+    const PushArgs* pu;
+    const Ctl* ctl;
+    long long P;
+    __device__ void operator()(int, T*& X, T*& V, const PushArgs*& p, const Ctl*& c, long long& Pp) const
+    {
+        X = xs; V = vs; p = pu; c = ctl; Pp = P;
+    }
+};
+
+template <typename T>
+__global__ __launch_bounds__(64) void reinject_kernel(T* __restrict__ xs, T* __restrict__ vs, PushArgs pu,
+                                                     const Ctl* __restrict__ ctl, LostList lost_list)
+{
+    reinject_list<T>(lost_list, OneSystem<T>{xs, vs, &pu, ctl, pu.Npad});
+}
 // ---------------------------------------------------------------------------
 // Initial state of ion i: uniform in the cylinder outside every grain,
 // velocity from N((0,0,u), sig^2).  Padding slots get a far-away sentinel

@@ -7,11 +7,13 @@
 //             parked at a far-away sentinel;
 //   a         [nsplit][3][Npad] partial accelerations of the source splits;
 //   ev        [Npad] per-ion event byte of the last step;
-//   lost      [Npad] indices of the ions the last push removed;
+//   lost      [Npad] (system, ion) pairs of the ions the step lost;
 //   ctl       small control block (charges, int64 fixed-point accumulators,
 //             last-step record, running sums, step counter, status word).
-// All per-step state stays on the device; a step is four launches (pair
-// forces, push, reinjection, finalize) and needs no host synchronisation.
+// All per-step state stays on the device; a step is three launches (pair sum;
+// the per-ion tail, whose last block finalizes the step; reinjection of the
+// ions the tail listed; a cutoff adds the slab sort and its epilogue) and
+// needs no host synchronisation.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -39,7 +41,6 @@ constexpr double kPI = 3.14159265358979323846;
 constexpr int kPairBlock = 256;
 constexpr int kPairTile = 256;
 constexpr int kPad = 256;
-constexpr int kReinjGrid = 2 * odk::kSlots;   // a multiple of the lost-list segments
 constexpr int kMaxSplitSingle = 4;             // source splits of one system's pair sum
 constexpr int kConfNr = 32, kConfNz = 32;      // intervals of the confinement grid along r, z
 constexpr int kConfNodes = (kConfNr + 1) * (kConfNz + 1);
@@ -129,7 +130,7 @@ struct od_system {
     void* v = nullptr;
     void* a = nullptr;
     uint8_t* ev = nullptr;
-    int* lost = nullptr;
+    int2* lost = nullptr;                // ions lost in the step, for the reinjection kernel
     odk::Ctl* ctl = nullptr;
     // timing
     bool timing = false;
@@ -182,19 +183,24 @@ void free_sym(od_system* s)
     s->sym = false;
 }
 
+// Sets up the symmetric pair sum: its fixed-point totals and work items.  In
+// test-particle mode there are no items (no pair kernel runs); the totals stay
+// zero and the step's tail adds the grain, drive and confinement terms.
 od_status setup_sym(od_system* s)
 {
     if (s->sym) return OD_OK;
     const int T = (int)(s->Npad / kPairBlock);
-    std::vector<odk::SymItem> items = sym_items(T);
+    std::vector<odk::SymItem> items;
+    if (s->pa.ion_ion) items = sym_items(T);
     s->acc_fix = (unsigned long long*)dev_alloc(s, 3 * (size_t)s->Npad * sizeof(unsigned long long));
-    s->sym_items = (odk::SymItem*)dev_alloc(s, items.size() * sizeof(odk::SymItem));
-    if (!s->acc_fix || !s->sym_items) {
+    if (!items.empty()) s->sym_items = (odk::SymItem*)dev_alloc(s, items.size() * sizeof(odk::SymItem));
+    if (!s->acc_fix || (!items.empty() && !s->sym_items)) {
         free_sym(s);
         return fail(OD_ENOMEM, "device allocation of the symmetric pair sum failed");
     }
-    HIPCHK(hipMemcpyAsync(s->sym_items, items.data(), items.size() * sizeof(odk::SymItem),
-                          hipMemcpyHostToDevice, s->stream));
+    if (!items.empty())
+        HIPCHK(hipMemcpyAsync(s->sym_items, items.data(), items.size() * sizeof(odk::SymItem),
+                              hipMemcpyHostToDevice, s->stream));
     HIPCHK(hipMemsetAsync(s->acc_fix, 0, 3 * (size_t)s->Npad * sizeof(unsigned long long), s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
     s->n_sym_items = (int)items.size();
@@ -206,7 +212,7 @@ od_status setup_sym(od_system* s)
 // unless one-sided is asked for (it is the faster at every size).
 od_status apply_pair_kind(od_system* s)
 {
-    const bool able = s->prec == OD_PREC_FP32 && s->pa.ion_ion;
+    const bool able = s->prec == OD_PREC_FP32;
     const bool want = able && (s->pair_kind == OD_PAIR_SYMMETRIC || s->pair_kind == OD_PAIR_AUTO);
     if (want && !s->sym) {
         od_status st = setup_sym(s);
@@ -496,6 +502,17 @@ hipEvent_t next_event(od_system* s)
 
 od_status launch_step(od_system* s, bool timed);
 
+// Blocks of 64 threads of the reinjection kernel for `ions` ions: one thread
+// per 128 ions, several times the ions lost in a step of the configurations
+// (about 0.2 % of N at Mach 1); the kernel walks the list with a grid stride,
+// so a longer list is still covered.
+// Systems up to this size reinject their lost ions inside the tail kernel
+// (a step is then two launches); larger ones list them for reinject_kernel,
+// which keeps the FP64 sampling out of the streaming tail's register budget.
+constexpr int64_t kInlineReinjectMaxN = 16384;
+
+int reinject_grid(int64_t ions) { return (int)std::min<int64_t>(1024, std::max<int64_t>(1, (ions + 8191) / 8192)); }
+
 void drop_graph(od_system* s)
 {
     if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
@@ -526,8 +543,10 @@ od_status capture_graph(od_system* s)
 od_status launch_step(od_system* s, bool timed)
 {
     const int gp = (int)(s->Npad / kPairBlock);
-    const int gq = (int)((s->N + 255) / 256);
-    for (int k = 0; k < 4; ++k) {
+    const int gt = (int)(s->Npad / 256);      // tail blocks
+    const odk::LostList lost{s->ctl->lost_seg, &s->ctl->lost_ticket, s->lost, odk::lost_cap(gt)};
+    const bool inl = s->N <= kInlineReinjectMaxN;
+    for (int k = 0; k < (inl ? 2 : 3); ++k) {
         int e0 = -1, e1 = -1;
         if (timed) {
             e0 = (int)s->evnext;
@@ -550,11 +569,10 @@ od_status launch_step(od_system* s, bool timed)
             odk::pair_cut_epilogue<<<nb, 256, 0, s->stream>>>(s->xs_sorted, s->idx_sorted, s->cut_fix,
                                                                (float*)s->a, s->pa, s->ds, s->ctl);
         } else if (k == 0 && s->sym) {
-            odk::pair_sym_kernel<kPairBlock><<<s->n_sym_items, kPairBlock, 0, s->stream>>>(
-                (const float*)s->x, (int)s->Npad, (int)s->N, s->pa.sym_scale, s->sym_items, s->acc_fix,
-                s->ctl);
-            odk::pair_sym_epilogue<<<(int)(s->Npad / 256), 256, 0, s->stream>>>(
-                (const float*)s->x, s->acc_fix, (float*)s->a, s->pa, s->ds, s->ctl);
+            if (s->n_sym_items > 0)     // none in test-particle mode
+                odk::pair_sym_kernel<kPairBlock><<<s->n_sym_items, kPairBlock, 0, s->stream>>>(
+                    (const float*)s->x, (int)s->Npad, (int)s->N, s->pa.sym_scale, s->sym_items, s->acc_fix,
+                    s->ctl);
         } else if (k == 0) {
             if (s->prec == OD_PREC_FP32)
                 odk::pair_forces_f32<kPairBlock, kPairTile><<<gp * s->nsplit, kPairBlock, 0, s->stream>>>(
@@ -562,24 +580,38 @@ od_status launch_step(od_system* s, bool timed)
             else
                 odk::pair_forces_f64<kPairBlock, kPairTile><<<gp, kPairBlock, 0, s->stream>>>(
                     (const double*)s->x, (double*)s->a, s->pa, s->ds, s->ctl);
+        } else if (k == 1 && s->sym && !s->cut && inl) {
+            odk::step_tail_kernel<float, true, true><<<gt, 256, 0, s->stream>>>(
+                (float*)s->x, (float*)s->v, (float*)s->a, s->acc_fix, s->ev, 1, s->pa, s->pu, s->ds, s->fa,
+                s->ctl, lost);
+        } else if (k == 1 && s->sym && !s->cut) {
+            odk::step_tail_kernel<float, true, false><<<gt, 256, 0, s->stream>>>(
+                (float*)s->x, (float*)s->v, (float*)s->a, s->acc_fix, s->ev, 1, s->pa, s->pu, s->ds, s->fa,
+                s->ctl, lost);
+        } else if (k == 1 && s->prec == OD_PREC_FP32 && inl) {
+            odk::step_tail_kernel<float, false, true><<<gt, 256, 0, s->stream>>>(
+                (float*)s->x, (float*)s->v, (float*)s->a, nullptr, s->ev, eff_split(s), s->pa, s->pu, s->ds,
+                s->fa, s->ctl, lost);
+        } else if (k == 1 && s->prec == OD_PREC_FP32) {
+            odk::step_tail_kernel<float, false, false><<<gt, 256, 0, s->stream>>>(
+                (float*)s->x, (float*)s->v, (float*)s->a, nullptr, s->ev, eff_split(s), s->pa, s->pu, s->ds,
+                s->fa, s->ctl, lost);
+        } else if (k == 1 && inl) {
+            odk::step_tail_kernel<double, false, true><<<gt, 256, 0, s->stream>>>(
+                (double*)s->x, (double*)s->v, (double*)s->a, nullptr, s->ev, 1, s->pa, s->pu, s->ds, s->fa,
+                s->ctl, lost);
         } else if (k == 1) {
-            if (s->prec == OD_PREC_FP32)
-                odk::push_kernel<float><<<gq, 256, 0, s->stream>>>(
-                    (float*)s->x, (float*)s->v, (const float*)s->a, s->ev, s->lost, s->pu, s->ds,
-                    s->ctl, eff_split(s));
-            else
-                odk::push_kernel<double><<<gq, 256, 0, s->stream>>>(
-                    (double*)s->x, (double*)s->v, (const double*)s->a, s->ev, s->lost, s->pu, s->ds,
-                    s->ctl, 1);
-        } else if (k == 2) {
-            if (s->prec == OD_PREC_FP32)
-                odk::reinject_kernel<float><<<kReinjGrid, 64, 0, s->stream>>>(
-                    (float*)s->x, (float*)s->v, s->lost, s->pu, odk::seg_cap(gq), s->ctl);
-            else
-                odk::reinject_kernel<double><<<kReinjGrid, 64, 0, s->stream>>>(
-                    (double*)s->x, (double*)s->v, s->lost, s->pu, odk::seg_cap(gq), s->ctl);
+            odk::step_tail_kernel<double, false, false><<<gt, 256, 0, s->stream>>>(
+                (double*)s->x, (double*)s->v, (double*)s->a, nullptr, s->ev, 1, s->pa, s->pu, s->ds, s->fa,
+                s->ctl, lost);
+        } else if (inl) {
+            // reinjected inside the tail
+        } else if (s->prec == OD_PREC_FP32) {
+            odk::reinject_kernel<float><<<reinject_grid(s->Npad), 64, 0, s->stream>>>(
+                (float*)s->x, (float*)s->v, s->pu, s->ctl, lost);
         } else {
-            odk::finalize_kernel<<<1, 64, 0, s->stream>>>(s->fa, s->ds, s->ctl);
+            odk::reinject_kernel<double><<<reinject_grid(s->Npad), 64, 0, s->stream>>>(
+                (double*)s->x, (double*)s->v, s->pu, s->ctl, lost);
         }
         HIPCHK(hipGetLastError());
         if (timed) {
@@ -669,7 +701,7 @@ od_status od_init_system(const od_plasma* plasma, const od_sim* sim, const od_du
     s->v = dev_alloc(s, vec);
     s->a = dev_alloc(s, vec * (s->prec == OD_PREC_FP32 ? kMaxSplitSingle : 1));
     s->ev = (uint8_t*)dev_alloc(s, (size_t)s->Npad);
-    s->lost = (int*)dev_alloc(s, (size_t)odk::kSlots * odk::seg_cap((int)((s->N + 255) / 256)) * sizeof(int));
+    s->lost = (int2*)dev_alloc(s, (size_t)odk::kSlots * odk::lost_cap(s->Npad / 256) * sizeof(int2));
     s->ctl = (odk::Ctl*)dev_alloc(s, sizeof(odk::Ctl));
     if (!s->x || !s->v || !s->a || !s->ev || !s->lost || !s->ctl) {
         od_destroy(s);
@@ -1016,8 +1048,8 @@ od_status od_set_pair_kernel(od_system* s, int32_t kind)
     if (!s) return fail(OD_EINVAL, "null system");
     if (kind != OD_PAIR_AUTO && kind != OD_PAIR_ONE_SIDED && kind != OD_PAIR_SYMMETRIC)
         return fail(OD_EINVAL, "unknown pair kernel kind %d", kind);
-    if (kind == OD_PAIR_SYMMETRIC && (s->prec != OD_PREC_FP32 || !s->pa.ion_ion))
-        return fail(OD_EINVAL, "the symmetric sum needs FP32 and the ion-ion force");
+    if (kind == OD_PAIR_SYMMETRIC && s->prec != OD_PREC_FP32)
+        return fail(OD_EINVAL, "the symmetric sum needs FP32");
     HIPCHK(hipStreamSynchronize(s->stream));
     drop_graph(s);
     const int old = s->pair_kind;

@@ -18,9 +18,9 @@
 //     tile, and the targets' sums once per item.
 // Fixed-point integer addition is exact and commutative, so the totals do
 // not depend on the order in which items run: results are deterministic.
-// A per-ion epilogue kernel converts the totals, adds the grain, drive and
-// confinement terms and the Eq. (1) sums (pair_epilogue), and clears the
-// accumulators for the next step.
+// The step's tail kernel converts the totals, adds the grain, drive and
+// confinement terms and the Eq. (1) sums, and clears the accumulators for
+// the next step.
 #pragma once
 
 #include "kernels.hpp"
@@ -67,14 +67,15 @@ __device__ __forceinline__ float rotate_down(float v)
 }
 
 // One work item of one system (positions X, Y, Z; N ions): target tile row
-// I against source tiles [J0, J1), J0 >= I.  Reactions go to
-// fix[c * stride + j], the targets' sums to fix[c * stride + i] (indices
-// local to the system).  pair(d) is the scalar f of the term f d.
+// I against the 64-ion sub-tiles [st0, st1) of the source tiles [J0, J1),
+// J0 >= I.  Reactions go to fix[c * stride + j], the targets' sums to
+// fix[c * stride + i] (indices local to the system).  pair(d) is the scalar
+// f of the term f d.
 template <int BLOCK, typename Pair>
 __device__ __forceinline__ void sym_item(const float* __restrict__ X, const float* __restrict__ Y,
                                          const float* __restrict__ Z, int N, int I, int J0, int J1,
-                                         unsigned long long* __restrict__ fix, long long stride,
-                                         double scale, int* status, float4 (*src)[128],
+                                         int st0, int st1, unsigned long long* __restrict__ fix,
+                                         long long stride, double scale, int* status, float4 (*src)[128],
                                          float (*jpart)[3][BLOCK], const Pair& pair)
 {
     static_assert(BLOCK == 256, "four waves of 64");
@@ -94,7 +95,7 @@ __device__ __forceinline__ void sym_item(const float* __restrict__ X, const floa
         __syncthreads();
         float ax = 0.0f, ay = 0.0f, az = 0.0f;
         if (J == I) {
-            for (int k = 0; k < BLOCK; ++k) {
+            for (int k = 64 * st0; k < 64 * st1; ++k) {
                 const float4 q = src[k >> 6][k & 63];
                 const float dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
                 float f = pair(dx, dy, dz);
@@ -104,7 +105,7 @@ __device__ __forceinline__ void sym_item(const float* __restrict__ X, const floa
                 az = fmaf(f, dz, az);
             }
         } else {
-            for (int st = 0; st < 4; ++st) {
+            for (int st = st0; st < st1; ++st) {
                 float jx = 0.0f, jy = 0.0f, jz = 0.0f;
                 const float4* base = &src[st][lane];
 #pragma unroll 16
@@ -127,7 +128,8 @@ __device__ __forceinline__ void sym_item(const float* __restrict__ X, const floa
             }
             __syncthreads();
             const int j = j0 + threadIdx.x;
-            if (j < N) {
+            const int jst = threadIdx.x >> 6;        // the source's sub-tile
+            if (j < N && jst >= st0 && jst < st1) {
                 for (int c = 0; c < 3; ++c) {
                     const float v = ((jpart[0][c][threadIdx.x] + jpart[1][c][threadIdx.x]) +
                                      jpart[2][c][threadIdx.x]) + jpart[3][c][threadIdx.x];
@@ -160,7 +162,7 @@ __device__ __forceinline__ void sym_rows(const float* __restrict__ X, const floa
 {
     if (J0 == I) {
         for (int r = 0; r < R; ++r)
-            sym_item<BLOCK>(X, Y, Z, N, I + r, I + r, I + R, fix, stride, scale, status, src, jpart, pair);
+            sym_item<BLOCK>(X, Y, Z, N, I + r, I + r, I + R, 0, 4, fix, stride, scale, status, src, jpart, pair);
         J0 = I + R;
     }
     if (J0 >= J1) return;
@@ -249,14 +251,14 @@ __device__ __forceinline__ void sym_rows(const float* __restrict__ X, const floa
 template <int BLOCK, typename Pair>
 __device__ __forceinline__ void sym_dispatch(const float* __restrict__ X, const float* __restrict__ Y,
                                              const float* __restrict__ Z, int N, int rows, int I, int J0,
-                                             int J1, unsigned long long* __restrict__ fix, long long stride,
-                                             double scale, int* status, float4 (*src)[128],
+                                             int J1, int st0, int st1, unsigned long long* __restrict__ fix,
+                                             long long stride, double scale, int* status, float4 (*src)[128],
                                              float (*jpart)[3][BLOCK], const Pair& pair)
 {
     if (rows == kSymRows)
         sym_rows<BLOCK, kSymRows>(X, Y, Z, N, I, J0, J1, fix, stride, scale, status, src, jpart, pair);
     else
-        sym_item<BLOCK>(X, Y, Z, N, I, J0, J1, fix, stride, scale, status, src, jpart, pair);
+        sym_item<BLOCK>(X, Y, Z, N, I, J0, J1, st0, st1, fix, stride, scale, status, src, jpart, pair);
 }
 
 template <int BLOCK>
@@ -268,30 +270,8 @@ void pair_sym_kernel(const float* __restrict__ xs, int Npad, int N, double scale
     __shared__ float4 src[4][128];          // sub-tiles of 64 sources, each stored twice
     __shared__ float jpart[4][3][BLOCK];    // reactions per wave
     const SymItem it = items[blockIdx.x];
-    sym_dispatch<BLOCK>(xs, xs + Npad, xs + 2 * Npad, N, it.rows, it.I, it.J0, it.J1, acc_fix, Npad, scale,
-                        &ctl->status, src, jpart, PlainPair{});
-}
-
-// Per ion: total of the pair sums, then the terms of pair_epilogue; clears
-// the accumulators (every slot of the Npad planes).
-__global__ __launch_bounds__(256) void pair_sym_epilogue(const float* __restrict__ xs,
-                                                         unsigned long long* __restrict__ acc_fix,
-                                                         float* __restrict__ acc, PairArgs p,
-                                                         DustSet ds, Ctl* __restrict__ ctl)
-{
-    __shared__ double red[4][kMaxDust][3];
-    const int Npad = p.Npad;
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    const bool live = i < p.N;
-    const float xi = xs[i], yi = xs[Npad + i], zi = xs[2 * Npad + i];
-    double s[3];
-    for (int c = 0; c < 3; ++c) {
-        unsigned long long* a = &acc_fix[(long long)c * Npad + i];
-        s[c] = live ? from_fixed(*a, p.sym_scale) : 0.0;
-        *a = 0ull;
-    }
-    pair_epilogue<256>(xi, yi, zi, i, live, p.Cd * s[0], p.Cd * s[1], p.Cd * s[2], true, p, ds, ctl,
-                       acc, acc + Npad, acc + 2 * Npad, red);
+    sym_dispatch<BLOCK>(xs, xs + Npad, xs + 2 * Npad, N, it.rows, it.I, it.J0, it.J1, it.st0, it.st1, acc_fix,
+                        Npad, scale, &ctl->status, src, jpart, PlainPair{});
 }
 
 }  // namespace odk

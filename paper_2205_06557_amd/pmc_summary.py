@@ -25,8 +25,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ("csrc/kernels.hpp", "csrc/device_common.hpp", "csrc/cutoff.hpp", "csrc/pairsym.hpp",
                   "csrc/worksplit.hpp", "csrc/symitems.hpp")
 CALIB_BYTES = 1 << 28
-KERNELS = {"pair_forces_f32": "pair", "pair_sym_kernel": "pair", "pair_sym_epilogue": "pair_epilogue",
-           "push_kernel<float>": "push", "reinject_kernel<float>": "reinject", "finalize_kernel": "finalize"}
+KERNELS = {"pair_forces_f32": "pair", "pair_sym_kernel": "pair", "step_tail_kernel<float, true>": "tail",
+           "step_tail_kernel<float, false>": "tail"}
 
 
 def kernel_sources_hash() -> str:

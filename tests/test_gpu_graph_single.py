@@ -80,7 +80,7 @@ def test_graph_with_timing_launches_singly(B):
         g.step(10)
         g.sync()
         kt = g.kernel_times()
-        assert kt["pair"][1] == 10 and kt["push"][1] == 10      # per-kernel launches, no graph
+        assert kt["pair"][1] == 10 and kt["tail"][1] == 10      # per-kernel launches, no graph
         g.set_timing(False)
         g.step(10)
         e.step(20)

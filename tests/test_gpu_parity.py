@@ -93,16 +93,19 @@ def test_many_absorptions(B):
         say("  ", r)
 
 
-def test_many_exits_and_reinjections(B):
-    w = W.single_grain_small().with_(n_ions=1 << 13, mach=0.5)
-    say("wall shell", w.name)
+# up to 16384 ions the tail kernel reinjects lost ions itself, above that a
+# separate kernel walks the list of lost ions
+@pytest.mark.parametrize("n_ions", [1 << 13, 20000])
+def test_many_exits_and_reinjections(B, n_ions):
+    w = W.single_grain_small().with_(n_ions=n_ions, mach=0.5)
+    say("wall shell", w.name, "N", n_ions)
     with B.System(w) as s:
         o = O.Oracle(w)
         x, v = W.wall_shell_state(w, w.n_ions)
         s.set_state(x.T / o.derived["lam"], v.T / o.derived["cs"], None, 11)
         r = shadow_step(s, o, w)
         say("  ", r)
-        assert r["n_exit"] > 1000
+        assert r["n_exit"] > n_ions // 8
 
 
 def test_test_particle_mode_and_literal_side(B):

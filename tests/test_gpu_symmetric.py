@@ -18,7 +18,9 @@ def B():
     return binding
 
 
-@pytest.mark.parametrize("n_ions", [2000, 257, 1037, 4096])
+# up to 4096 ions (16 tiles) the items are single 64-ion source sub-tiles,
+# at 12000 (47 tiles) whole tile pairs
+@pytest.mark.parametrize("n_ions", [2000, 257, 1037, 4096, 12000])
 def test_shadowed_steps_symmetric(B, n_ions):
     w = W.single_grain_small().with_(n_ions=n_ions)
     say("symmetric kernel, N", n_ions)
@@ -115,10 +117,15 @@ def test_selection_rules(B):
     with B.System(small, precision=B.PREC_FP64) as s:
         with pytest.raises(B.OdError):
             s.set_pair_kernel(B.PAIR_SYMMETRIC)
+    # test-particle mode: the symmetric setting (the default) runs no pair
+    # kernel, the one-sided one a grain-terms-only kernel
     tp = small.with_(flags=W.FLAG_NO_ION_ION)
     with B.System(tp) as s:
-        with pytest.raises(B.OdError):
-            s.set_pair_kernel(B.PAIR_SYMMETRIC)
+        assert s.pair_kernel() == B.PAIR_SYMMETRIC
+        s.set_pair_kernel(B.PAIR_ONE_SIDED)
+        assert s.pair_kernel() == B.PAIR_ONE_SIDED
+        s.set_pair_kernel(B.PAIR_SYMMETRIC)
+        assert s.pair_kernel() == B.PAIR_SYMMETRIC
 
 
 def _batch_systems():
