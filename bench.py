@@ -25,6 +25,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FLOP_PER_PAIR = 23            # algorithmic FP32 flop per ordered pair
+# FP32 flop the symmetric kernel executes per unordered pair: the 17 operations
+# of the pair term with its transcendental steps (difference 3, r^2 5, rsqrt 1,
+# r 1, exponent argument 1, exp 1, 1/r^2 1, (1 + r)/r^3 2, times e^-r 1) plus
+# 3 fused multiply-adds into the target's sum (6) and 3 into the source's
+# reaction (6): 28, against 2 x 23 = 46 for the two ordered pairs it covers.
+FLOP_PER_UNIQUE_PAIR = 28
 PEAK_FP32 = 157.3e12          # MI355X published FP32 vector peak (counts packed FP32)
 PEAK_FP64 = 78.6e12           # MI355X published FP64 vector peak
 PEAK_HBM = 8.0e12             # MI355X HBM3E, B/s
@@ -43,6 +49,21 @@ def measured_traffic(kernel: str, n_ions: int):
         return None
     k = s.get("kernels", {}).get(kernel)
     return None if k is None else k["traffic_bytes"]
+
+
+def measured_issue(n_ions: int):
+    """VALU issue utilisation of the pair kernel (quad-cycles of issued VALU
+    instructions over the SIMDs' available quad-cycles) from the committed
+    instruction-counter summary, or None if absent, for another size, or the
+    kernel sources have changed since."""
+    from paper_2205_06557_amd import pmc_summary as P
+    path = os.path.join(ROOT, "profiles", "pair_sym_counters.json")
+    if not os.path.exists(path):
+        return None
+    s = json.load(open(path))
+    if s.get("source_sha256") != P.kernel_sources_hash() or s.get("n_ions") != n_ions:
+        return None
+    return s.get("valu_issue_frac")
 
 
 def copy_rate(nbytes: int, reps: int = 20) -> float:
@@ -76,24 +97,37 @@ def push_bytes_per_ion(prec: int) -> int:
 
 def cpu_baseline(w, sysm, target_s: float):
     """The FP64 oracle's force evaluation on a sample of target ions of the
-    same 2^20-ion state (every ion a source), scaled to ion-steps/s."""
+    same 2^20-ion state (every ion a source), scaled to ion-steps/s; and the
+    error of the GPU's accelerations at that state on the sampled targets."""
     import numpy as np
     from oracle import oracle as O
     o = O.Oracle(w, init=False)
     x, v, q, step = sysm.get_state()
-    lam, cs = o.derived["lam"], o.derived["cs"]
+    lam, cs, wpi = o.derived["lam"], o.derived["cs"], o.derived["wpi"]
     o.set_state(x.T.astype(np.float64) * lam, v.T.astype(np.float64) * cs, q, step)
+    sysm.step(1)                      # the GPU's forces at the same state (untimed)
+    a_gpu = sysm.accelerations().T.astype(np.float64) * lam * wpi * wpi
     rng = np.random.default_rng(0)
     o.accel_subset(rng.choice(w.n_ions, size=16, replace=False))      # threads up, caches warm
     order = rng.permutation(w.n_ions)
     m2, chunk, dt = 0, 256, 0.0
+    a_orc = []
     while dt < target_s and m2 + chunk <= w.n_ions:
         t0 = time.perf_counter()
-        o.accel_subset(order[m2:m2 + chunk])
+        a_orc.append(o.accel_subset(order[m2:m2 + chunk]))
         dt += time.perf_counter() - t0
         m2 += chunk
     pairs = m2 * (w.n_ions - 1)
     pps = pairs / dt
+    a_orc = np.concatenate(a_orc)
+    a_g = a_gpu[order[:m2]]
+    d = np.linalg.norm(a_g - a_orc, axis=1)
+    mag = np.linalg.norm(a_orc, axis=1)
+    rel = d / np.maximum(mag, math.sqrt(np.mean(mag ** 2)))
+    err = {"targets": int(m2), "rel_l2": float(np.linalg.norm(a_g - a_orc) / np.linalg.norm(a_orc)),
+           "p99_9": float(np.percentile(rel, 99.9)), "max": float(rel.max()),
+           "note": "GPU FP32 accelerations vs the FP64 oracle at the timed run's final state; per-ion "
+                   "error over max(|a_i|, rms |a|)"}
     return {
         "value": pps / (w.n_ions - 1),
         "unit": "ion-steps/s",
@@ -103,7 +137,7 @@ def cpu_baseline(w, sysm, target_s: float):
                   f"the {w.n_ions}-ion state, all ions as sources ({pairs:.3e} pairs in {dt:.1f} s); "
                   f"ion-steps/s = pairs/s / (N-1); push, charging and reinjection are O(N) and omitted",
         "pairs_per_s": pps,
-    }
+    }, err
 
 
 FLOP_PER_CUT_PAIR = 40       # algorithmic FP32 flop per evaluated pair of the switched force
@@ -121,7 +155,9 @@ def cutoff_bench(args):
 
     torch.cuda.set_device(0)
     series = []
-    for lg in sorted(int(v) for v in args.cutoff_sizes.split(",")):
+    sizes = sorted(int(v) for v in args.cutoff_sizes.split(","))
+    max_lg = sizes[-1]
+    for lg in sizes:
         w = W.long_domain(1 << lg)
         s = B.System(w)
         s.set_cutoff(W.CUTOFF_SWITCH, W.CUTOFF_RADIUS)
@@ -136,12 +172,15 @@ def cutoff_bench(args):
         kt = s.kernel_times()
         s.set_timing(False)
         ns, npairs = s.cutoff_info()
+        within = pairs_within_cutoff(s, w, W.CUTOFF_RADIUS) if lg == max_lg else None
         s.close()
         pair_ms = kt["pair"][0] / max(kt["pair"][1], 1)
         row = {"n_ions": w.n_ions, "H_over_lambda": w.H / w.lam, "slabs": ns,
                "ms_per_step": 1e3 * wall / args.steps, "pair_ms": pair_ms,
                "pairs_evaluated": npairs, "sources_per_ion": npairs / w.n_ions,
                "ion_steps_per_s": w.n_ions * args.steps / wall}
+        if within is not None:
+            row["pairs_within_cutoff"] = within
         series.append(row)
         print(f"[bench] cutoff N=2^{lg}: {row['ms_per_step']:.2f} ms/step, "
               f"{row['sources_per_ion']:.0f} sources per ion", file=sys.stderr, flush=True)
@@ -150,6 +189,8 @@ def cutoff_bench(args):
     beta = float(np.polyfit(np.log(n), np.log(t), 1)[0]) if len(series) > 1 else None
     last = series[-1]
     achieved = FLOP_PER_CUT_PAIR * last["pairs_evaluated"] / (last["pair_ms"] * 1e-3)
+    within = last["pairs_within_cutoff"]
+    achieved_within = FLOP_PER_CUT_PAIR * within["ordered_pairs"] / (last["pair_ms"] * 1e-3)
     res = {
         "metric": "ion-steps/s with the ion-ion cutoff, constant-concentration series",
         "value": last["ion_steps_per_s"],
@@ -163,12 +204,37 @@ def cutoff_bench(args):
                    "n_ions": last["n_ions"]},
         "time_exponent_beta": beta,
         "series": series,
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
-                     "kernel": "slab sort + pair_cut (evaluated pairs)",
-                     "flop_per_pair": FLOP_PER_CUT_PAIR, "launch_ms": last["pair_ms"]},
+        "roofline": {"bound": "alu", "achieved": achieved_within / 1e12, "peak": PEAK_FP32 / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved_within / PEAK_FP32, "traffic": None,
+                     "kernel": "slab sort + pair_cut",
+                     "flop_per_pair": FLOP_PER_CUT_PAIR,
+                     "flop_convention": "ordered ion pairs closer than r_cut (the method's work), "
+                                        "estimated from sampled targets",
+                     "covered_pairs_frac": achieved / PEAK_FP32,
+                     "covered_convention": "every ordered pair of the 256-ion sorted blocks the "
+                                           "kernel covers, padding and pairs beyond r_cut included",
+                     "launch_ms": last["pair_ms"]},
     }
     print(json.dumps(res), flush=True)
+
+
+def pairs_within_cutoff(sysm, w, r_cut, n_targets=256, seed=0):
+    """Ordered ion pairs closer than r_cut at the system's current state,
+    estimated from n_targets random target ions (each against every other
+    ion, exact distances in FP64): N times the mean count, with its standard
+    error."""
+    import numpy as np
+    x = sysm.get_state()[0].astype(np.float64)           # [3][N], units of r_De
+    rc = r_cut / w.lam
+    rng = np.random.default_rng(seed)
+    counts = []
+    for i in rng.choice(x.shape[1], size=n_targets, replace=False):
+        d2 = ((x - x[:, i:i + 1]) ** 2).sum(axis=0)
+        counts.append(int(np.count_nonzero(d2 < rc * rc)) - 1)
+    c = np.asarray(counts, dtype=np.float64)
+    n = x.shape[1]
+    return {"ordered_pairs": float(n * c.mean()), "std_error": float(n * c.std(ddof=1) / math.sqrt(len(c))),
+            "targets_sampled": n_targets}
 
 
 def crossover_bench(args):
@@ -212,47 +278,6 @@ def crossover_bench(args):
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
                      "kernel": "pair_sym_kernel at the largest N", "flop_per_pair": FLOP_PER_PAIR},
-    }
-    print(json.dumps(res), flush=True)
-
-
-def paper_case1_bench(args):
-    """The paper's first test case (Table 2: 2^16 ions, one grain with a preset
-    charge, collisionless Mach 1 flow, 3000 steps) run whole: wall time of the
-    3000 steps, for comparison with the run times the paper quotes for its
-    GPUs (context, not a target)."""
-    import torch
-    from paper_2205_06557_amd import binding as B
-    from paper_2205_06557_amd import workloads as W
-
-    torch.cuda.set_device(0)
-    w = W.paper_table2()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s = B.System(w)
-    s.sync()
-    setup = time.perf_counter() - t0
-    t1 = time.perf_counter()
-    s.step(w.n_steps)
-    s.sync()
-    run = time.perf_counter() - t1
-    q, _ = s.charges()
-    F = s.forces(1)
-    s.close()
-    n = w.n_ions
-    res = {
-        "metric": "wall time of the paper's test case 1 (Table 2), 3000 steps",
-        "value": run, "unit": "s", "n_gpus": 1, "steps": w.n_steps, "warmup": 0,
-        "ms_per_step": 1e3 * run / w.n_steps, "higher_is_better": False, "scaling": "strong",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "paper Table 2: N = 2^16, grain r = 58.8 um at z = -1 r_De with "
-                               "charge 392,500 e, collisionless Mach 1, R = 3 r_De, H = 6 r_De, "
-                               "dt = 3.5148e-10 s", "n_ions": n},
-        "setup_s": setup,
-        "ion_steps_per_s": n * w.n_steps / run,
-        "pair_interactions_per_s": n * (n - 1) * w.n_steps / run,
-        "grain_charge_e": float(q[0]) / 1.602176634e-19,
-        "time_averaged_force_N": {"orbit_z": float(F[0, 0, 2]), "collect_z": float(F[0, 2, 2])},
     }
     print(json.dumps(res), flush=True)
 
@@ -391,12 +416,7 @@ def main():
                     help="pair-phase times of the one-sided and symmetric kernels, 2^12 .. 2^20 ions")
     ap.add_argument("--graph", action="store_true",
                     help="small single systems: single launches against HIP-graph replay")
-    ap.add_argument("--paper-case1", action="store_true",
-                    help="the paper's test case 1 (Table 2) run whole: wall time of 3000 steps")
     args = ap.parse_args()
-    if args.paper_case1 and args.gpus == 1:
-        paper_case1_bench(args)
-        return
     if args.graph and args.gpus == 1:
         graph_bench(args)
         return
@@ -462,7 +482,9 @@ def main():
     pairs = N * (N - 1) * args.steps / wall
     pair_ms = kt["pair"][0] / max(kt["pair"][1], 1)
     push_ms = kt["tail"][0] / max(kt["tail"][1], 1)
+    rein_ms = kt["reinject"][0] / max(kt["reinject"][1], 1)
     achieved = FLOP_PER_PAIR * N * (N - 1) / (pair_ms * 1e-3)
+    executed = FLOP_PER_UNIQUE_PAIR * N * (N - 1) / 2 / (pair_ms * 1e-3)
     peak = PEAK_FP64 if prec else PEAK_FP32
     push_gbs = push_bytes_per_ion(prec) * N / (push_ms * 1e-3)
     q, _ = sysm.charges()
@@ -493,27 +515,35 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / peak,
             "traffic": None if prec else measured_traffic("pair", N),
-            "kernel": "pair_forces_f64" if prec else "pair_forces",
+            "kernel": "pair_forces_f64" if prec else "pair_sym_kernel",
             "flop_per_pair": FLOP_PER_PAIR,
+            "flop_convention": "algorithmic: 23 flop per ordered pair, N(N-1) pairs per launch",
             "launch_ms": pair_ms,
         },
-        "push_roofline": {
+        "tail_roofline": {
             "bound": "hbm",
             "achieved": push_gbs / 1e9,
             "peak": PEAK_HBM / 1e9,
             "unit": "GB/s",
             "frac": push_gbs / PEAK_HBM,
-            "traffic": None if prec else measured_traffic("push", N),
+            "traffic": None if prec else measured_traffic("tail", N),
             "bytes_per_ion": push_bytes_per_ion(prec),
+            "kernel": "step_tail_kernel",
             "launch_ms": push_ms,
         },
-        "kernel_ms": {"pair": pair_ms, "tail": push_ms},
+        "kernel_ms": {"pair": pair_ms, "tail": push_ms, "reinject": rein_ms},
         "dust_charge_e": [float(x) / 1.602176634e-19 for x in q],
     }
-    res["push_roofline"]["copy_reference_gbs"] = copy_rate(push_bytes_per_ion(prec) * N)
+    if not prec:
+        # the work the symmetric kernel executes: each unordered pair once
+        res["roofline"]["executed"] = {
+            "flop_per_unique_pair": FLOP_PER_UNIQUE_PAIR, "unique_pairs": N * (N - 1) // 2,
+            "achieved": executed / 1e12, "unit": "TFLOP/s", "frac": executed / PEAK_FP32,
+            "valu_issue_frac": measured_issue(N)}
+    res["tail_roofline"]["copy_reference_gbs"] = copy_rate(push_bytes_per_ion(prec) * N)
     if not args.no_cpu:
         print("[bench] timing the CPU oracle on a sample ...", file=sys.stderr, flush=True)
-        res["cpu_baseline"] = cpu_baseline(w, sysm, args.cpu_seconds)
+        res["cpu_baseline"], res["gpu_vs_oracle_accel_error"] = cpu_baseline(w, sysm, args.cpu_seconds)
     sysm.close()
     print(json.dumps(res), flush=True)
 

@@ -159,7 +159,14 @@ void od_destroy(od_system* sys);
 /* Thread-local text of the last error. */
 const char* od_last_error(void);
 
-/* ---- inspection and test surface --------------------------------------- */
+/* ---- inspection and test surface ---------------------------------------
+ * The calls of this section expose the state, the events of a step and the
+ * library's own choices (pair kernel, source splits, timing) for tests,
+ * measurement and checkpointing.  The paper's interface is the parameter
+ * objects and per-grain observables above; a call below cites a passage only
+ * where one defines what it returns (the cutoff of Section 4, the
+ * confinement field of Appendix A, the absorbed ions and the history of
+ * Sections 2 and 3); the others have none. */
 
 /* Units of the dimensionless state: units_host[4] = {length r_De (m),
  * time 1/omega_pi (s), velocity c_s = r_De omega_pi (m/s),
@@ -263,18 +270,46 @@ od_status od_get_pair_split(od_system* sys, int32_t* nsplit);
 
 /* Events of the last step: ev_host[N] bytes (0 none, 1 exited, 2 + d
  * absorbed by grain d; bit 7 set if a charge-exchange collision happened),
- * n_abs_host[n_dust] absorbed counts, *n_exit, *n_coll.  Any may be NULL. */
+ * n_abs_host[n_dust] absorbed counts, *n_exit, *n_coll.  Any may be NULL.
+ * Test surface (the per-ion view of the events of Section 2). */
 od_status od_get_step_events(od_system* sys, uint8_t* ev_host, int64_t* n_abs_host,
                              int64_t* n_exit, int64_t* n_coll);
 
+/* Ions absorbed in the last step (Section 2: an ion whose drift segment
+ * meets a grain's surface is absorbed by that grain and delivers its charge
+ * and momentum, Eq. (3)): absorbed_host[k] the ion index and by_dust_host[k]
+ * the grain, for k < min(*n_absorbed, cap), in increasing ion order;
+ * *n_absorbed the total, which may exceed cap; *n_exited the ions that left
+ * through the cylinder's surface.  Any pointer may be NULL.  Synchronises. */
+od_status od_get_absorbed(od_system* sys, int64_t* absorbed_host, int32_t* by_dust_host, int64_t cap,
+                          int64_t* n_absorbed, int64_t* n_exited);
+
+/* Per-step history of the observables of Section 3 (the charge q(n) and the
+ * four force parts of Eqs. (1)-(4) of every step), kept on the device.
+ * od_set_history(sys, capacity) records the next `capacity` steps, from the
+ * current step counter on (0 turns recording off and frees the buffer;
+ * capacity * n_dust * 14 doubles of device memory); it drops a captured graph
+ * and synchronises.  od_get_history copies the records out:
+ * rec_host[k][n_dust][14] for the k-th recorded step = {Q^n (C), the twelve
+ * force components of od_get_dust_forces (N), absorbed count}, and sets
+ * *n_recorded (at most capacity).  rec_host may be NULL. */
+od_status od_set_history(od_system* sys, int64_t capacity);
+od_status od_get_history(od_system* sys, double* rec_host, int64_t* n_recorded);
+
 /* One Philox4x64-10 block computed on the device: out_host[4] for counter
- * ctr_host[4] and key (seed, system). */
+ * ctr_host[4] and key (seed, system).  Test surface: no passage of the paper
+ * defines it (the paper specifies no random generator); it lets a test check
+ * the device generator against a reference implementation. */
 od_status od_rng_block(uint64_t seed, uint64_t system, const uint64_t* ctr_host, uint64_t* out_host);
 
-/* Kernel timing with HIP events on the system's stream.  While enabled,
- * od_step brackets every launch; od_get_kernel_times synchronises and
- * returns, per kernel class {0 pair forces, 1 push, 2 reinjection,
- * 3 finalize}, the summed milliseconds ms_host[4] and launch counts
+/* Kernel timing with HIP events on the system's stream (measurement
+ * surface, no paper passage).  While enabled, od_step brackets every launch;
+ * od_get_kernel_times synchronises and returns, per kernel class {0 pair
+ * forces (with a cutoff: the slab sort and its epilogue too), 1 the step's
+ * tail (acceleration of the symmetric sum, push, absorption, exit, and the
+ * charge and force bookkeeping of the step in its last block), 2 reinjection
+ * (systems above 16,384 ions; smaller ones reinject inside the tail), 3 not
+ * used}, the summed milliseconds ms_host[4] and launch counts
  * launches_host[4] since enabling, then resets them. */
 od_status od_set_timing(od_system* sys, int32_t enable);
 od_status od_get_kernel_times(od_system* sys, double* ms_host, int64_t* launches_host);
@@ -421,6 +456,16 @@ od_status od_mlp_predict(od_mlp* q, const float* X_host, int64_t n, float* Y_hos
  * the caller; calls in one stream are ordered by the stream. */
 #define OD_MLP_NOALLOC_MAX_ROWS 1024
 od_status od_mlp_predict_noalloc(od_mlp* q, const float* X_dev, int64_t n, float* Y_dev, int32_t* inside_dev);
+/* The surrogate of the batched-solver study as two calls: od_surrogate_train
+ * creates a network (weights from Philox(seed)), maps inputs from the box
+ * [in_lo_host, in_hi_host] (5 floats each) to [-1, 1], standardises the 16
+ * outputs by the training set's mean and standard deviation, and trains it
+ * with Adam (cfg) on X_host[n][5], Y_host[n][16]; od_surrogate_predict is
+ * od_mlp_predict.  The network is released with od_mlp_destroy. */
+od_status od_surrogate_train(const float* X_host, const float* Y_host, int64_t n, const float* in_lo_host,
+                             const float* in_hi_host, const od_train_cfg* cfg, uint64_t seed, void* hip_stream,
+                             od_mlp** out);
+od_status od_surrogate_predict(od_mlp* q, const float* X_host, int64_t n, float* Y_host, int32_t* inside_host);
 /* Mean-squared error and its gradient (grad_host[35856]) on n <= 4096 rows of
  * already normalised inputs Xn_host[n][5] and standardised targets
  * Tn_host[n][16]. */

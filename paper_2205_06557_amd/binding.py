@@ -104,13 +104,18 @@ def lib():
         L.od_get_pair_kernel.argtypes = [vp, C.POINTER(C.c_int32)]
         L.od_get_cutoff_info.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
         L.od_set_graph.argtypes = [vp, C.c_int32]
+        L.od_get_absorbed.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32), i64, C.POINTER(C.c_int64),
+                                      C.POINTER(C.c_int64)]
+        L.od_set_history.argtypes = [vp, i64]
+        L.od_get_history.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         for name in ("od_init_system", "od_step", "od_sync", "od_get_dust_charges",
                      "od_get_dust_forces", "od_get_units", "od_get_sizes", "od_get_state",
                      "od_set_state", "od_get_accelerations", "od_get_step_events",
                      "od_rng_block", "od_set_timing", "od_get_kernel_times",
                      "od_get_confinement", "od_set_cutoff", "od_get_cutoff_info",
                      "od_set_pair_split", "od_get_pair_split", "od_set_pair_kernel",
-                     "od_get_pair_kernel", "od_set_graph"):
+                     "od_get_pair_kernel", "od_set_graph", "od_get_absorbed", "od_set_history",
+                     "od_get_history"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -299,6 +304,29 @@ class System:
         return ev, nabs[: self.nd], ne.value, nc.value
 
     # --- timing -------------------------------------------------------------
+    def absorbed(self, cap: Optional[int] = None):
+        """(ion indices, grains) of the ions absorbed in the last step, and the
+        number that exited."""
+        cap = self.N if cap is None else int(cap)
+        idx = np.zeros(max(cap, 1), dtype=np.int64)
+        by = np.zeros(max(cap, 1), dtype=np.int32)
+        na, ne = C.c_int64(0), C.c_int64(0)
+        _check(lib().od_get_absorbed(self._h, _ptr(idx, C.c_int64), _ptr(by, C.c_int32), cap, C.byref(na),
+                                     C.byref(ne)))
+        k = min(na.value, cap)
+        return idx[:k], by[:k], na.value, ne.value
+
+    def set_history(self, capacity: int):
+        _check(lib().od_set_history(self._h, int(capacity)))
+
+    def history(self):
+        """Per-step records [steps, n_dust, 14]: Q^n (C), 12 force components (N), absorbed count."""
+        n = C.c_int64(0)
+        _check(lib().od_get_history(self._h, None, C.byref(n)))
+        rec = np.zeros((max(n.value, 1), self.nd, 14))
+        _check(lib().od_get_history(self._h, _ptr(rec), C.byref(n)))
+        return rec[: n.value]
+
     def set_timing(self, enable: bool):
         _check(lib().od_set_timing(self._h, 1 if enable else 0))
 
@@ -484,6 +512,29 @@ class Batch:
                                                      _ptr(nabs, C.c_int64), C.byref(ne), C.byref(nc)))
         return ev, nabs[: len(self.ws[s].dust)], ne.value, nc.value
 
+    def absorbed(self, cap: Optional[int] = None):
+        """(ion indices, grains) of the ions absorbed in the last step, and the
+        number that exited."""
+        cap = self.N if cap is None else int(cap)
+        idx = np.zeros(max(cap, 1), dtype=np.int64)
+        by = np.zeros(max(cap, 1), dtype=np.int32)
+        na, ne = C.c_int64(0), C.c_int64(0)
+        _check(lib().od_get_absorbed(self._h, _ptr(idx, C.c_int64), _ptr(by, C.c_int32), cap, C.byref(na),
+                                     C.byref(ne)))
+        k = min(na.value, cap)
+        return idx[:k], by[:k], na.value, ne.value
+
+    def set_history(self, capacity: int):
+        _check(lib().od_set_history(self._h, int(capacity)))
+
+    def history(self):
+        """Per-step records [steps, n_dust, 14]: Q^n (C), 12 force components (N), absorbed count."""
+        n = C.c_int64(0)
+        _check(lib().od_get_history(self._h, None, C.byref(n)))
+        rec = np.zeros((max(n.value, 1), self.nd, 14))
+        _check(lib().od_get_history(self._h, _ptr(rec), C.byref(n)))
+        return rec[: n.value]
+
     def set_timing(self, enable: bool):
         _check(_batch_lib().od_batch_set_timing(self._h, 1 if enable else 0))
 
@@ -554,12 +605,14 @@ def _mlp_lib():
         L.od_mlp_set_normalization.argtypes = [vp, fp, fp, fp, fp]
         L.od_mlp_predict.argtypes = [vp, fp, i64, fp, C.POINTER(C.c_int32)]
         L.od_mlp_predict_noalloc.argtypes = [vp, vp, i64, vp, vp]
+        L.od_surrogate_train.argtypes = [fp, fp, i64, fp, fp, C.POINTER(TrainCfg), C.c_uint64, vp, C.POINTER(vp)]
+        L.od_surrogate_predict.argtypes = [vp, fp, i64, fp, C.POINTER(C.c_int32)]
         L.od_mlp_loss_grad.argtypes = [vp, fp, fp, i64, fp, dp]
         L.od_mlp_train.argtypes = [vp, fp, fp, i64, C.POINTER(TrainCfg), dp]
         L.od_oml_floating_charge.argtypes = [C.POINTER(Plasma), C.c_double, dp]
         for name in ("od_mlp_create", "od_mlp_get_params", "od_mlp_set_params", "od_mlp_set_normalization",
                      "od_mlp_predict", "od_mlp_predict_noalloc", "od_mlp_loss_grad", "od_mlp_train",
-                     "od_oml_floating_charge"):
+                     "od_oml_floating_charge", "od_surrogate_train", "od_surrogate_predict"):
             getattr(L, name).restype = C.c_int
         _mlp_sigs = True
     return L

@@ -132,6 +132,7 @@ struct od_system {
     uint8_t* ev = nullptr;
     int2* lost = nullptr;                // ions lost in the step, for the reinjection kernel
     odk::Ctl* ctl = nullptr;
+    double* hist = nullptr;              // per-step records (od_set_history), or null
     // timing
     bool timing = false;
     std::vector<hipEvent_t> evpool;
@@ -838,6 +839,7 @@ void od_destroy(od_system* s)
     dev_free(s, s->a);
     dev_free(s, s->ev);
     dev_free(s, s->lost);
+    dev_free(s, s->hist);
     dev_free(s, s->ctl);
     for (hipEvent_t e : s->evpool) (void)hipEventDestroy(e);
     delete s;
@@ -1098,6 +1100,71 @@ od_status od_get_step_events(od_system* s, uint8_t* ev, int64_t* n_abs, int64_t*
         for (int d = 0; d < s->nd; ++d) n_abs[d] = (int64_t)h.last[d][13];
     if (n_exit) *n_exit = h.last_exit;
     if (n_coll) *n_coll = h.last_coll;
+    return OD_OK;
+}
+
+od_status od_get_absorbed(od_system* s, int64_t* absorbed, int32_t* by_dust, int64_t cap, int64_t* n_absorbed,
+                          int64_t* n_exited)
+{
+    if (!s) return fail(OD_EINVAL, "null system");
+    if (cap < 0) return fail(OD_EINVAL, "cap < 0");
+    std::vector<uint8_t> ev((size_t)s->N);
+    HIPCHK(hipMemcpyAsync(ev.data(), s->ev, (size_t)s->N, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    int64_t na = 0, ne = 0;
+    for (int64_t i = 0; i < s->N; ++i) {
+        const int code = ev[(size_t)i] & 0x7f;
+        if (code == odk::kEvExit) {
+            ++ne;
+        } else if (code >= odk::kEvAbsBase) {
+            if (na < cap) {
+                if (absorbed) absorbed[na] = i;
+                if (by_dust) by_dust[na] = code - odk::kEvAbsBase;
+            }
+            ++na;
+        }
+    }
+    if (n_absorbed) *n_absorbed = na;
+    if (n_exited) *n_exited = ne;
+    return OD_OK;
+}
+
+od_status od_set_history(od_system* s, int64_t capacity)
+{
+    if (!s) return fail(OD_EINVAL, "null system");
+    if (capacity < 0 || capacity > ((int64_t)1 << 30)) return fail(OD_EINVAL, "capacity out of [0, 2^30]");
+    HIPCHK(hipStreamSynchronize(s->stream));
+    drop_graph(s);
+    dev_free(s, s->hist);
+    s->hist = nullptr;
+    s->fa.hist = nullptr;
+    s->fa.hist_cap = 0;
+    if (capacity == 0 || s->nd == 0) return OD_OK;
+    s->hist = (double*)dev_alloc(s, (size_t)capacity * s->nd * odk::kHistWords * sizeof(double));
+    if (!s->hist) return fail(OD_ENOMEM, "device allocation of the history failed");
+    odk::Ctl h;
+    HIPCHK(hipMemcpyAsync(&h, s->ctl, sizeof h, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->fa.hist = s->hist;
+    s->fa.hist_start = h.step;
+    s->fa.hist_cap = capacity;
+    return OD_OK;
+}
+
+od_status od_get_history(od_system* s, double* rec, int64_t* n_recorded)
+{
+    if (!s) return fail(OD_EINVAL, "null system");
+    odk::Ctl h;
+    HIPCHK(hipMemcpyAsync(&h, s->ctl, sizeof h, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    const int64_t n = s->hist ? std::max<int64_t>(0, std::min<int64_t>(h.step - s->fa.hist_start, s->fa.hist_cap)) : 0;
+    if (n_recorded) *n_recorded = n;
+    if (rec && n > 0) {
+        const size_t words = (size_t)n * s->nd * odk::kHistWords;
+        HIPCHK(hipMemcpyAsync(rec, s->hist, words * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+        for (size_t k = 0; k < words; k += odk::kHistWords) rec[k] *= kQE;   // charge e -> C
+    }
     return OD_OK;
 }
 

@@ -25,8 +25,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ("csrc/kernels.hpp", "csrc/device_common.hpp", "csrc/cutoff.hpp", "csrc/pairsym.hpp",
                   "csrc/worksplit.hpp", "csrc/symitems.hpp")
 CALIB_BYTES = 1 << 28
-KERNELS = {"pair_forces_f32": "pair", "pair_sym_kernel": "pair", "step_tail_kernel<float, true>": "tail",
-           "step_tail_kernel<float, false>": "tail"}
+KERNELS = {"pair_forces_f32": "pair", "pair_sym_kernel": "pair", "step_tail_kernel<float, ": "tail",
+           "reinject_kernel<float>": "reinject"}
 
 
 def kernel_sources_hash() -> str:
@@ -67,15 +67,47 @@ def summarise(fetch_csv, write_csv, n_ions):
     return out
 
 
+def summarise_issue(counters_csv, n_ions, kernel="pair_sym_kernel"):
+    """VALU issue accounting of `kernel` from one rocprofv3 --pmc run with
+    SQ_INSTS_VALU, SQ_INSTS_VALU_TRANS_F32, SQ_ACTIVE_INST_VALU,
+    SQ_ACTIVE_INST_VALU2 and GRBM_GUI_ACTIVE (per dispatch, averaged over the
+    kernel's dispatches).  SQ_ACTIVE_INST_VALU counts one quad-cycle per
+    ordinary and two per transcendental VALU instruction, summed over the
+    SIMDs; SQ_ACTIVE_INST_VALU2 the quad-cycles in which two issued together;
+    GRBM_GUI_ACTIVE the busy cycles summed over the 8 XCDs.  The issue
+    fraction is (ACTIVE_INST_VALU - ACTIVE_INST_VALU2) over the quad-cycles
+    the 1024 SIMDs had: 1024 * (GRBM_GUI_ACTIVE / 8) / 4."""
+    vals = collections.defaultdict(list)
+    for r in csv.DictReader(open(counters_csv)):
+        if kernel in r["Kernel_Name"]:
+            vals[r["Counter_Name"]].append(float(r["Counter_Value"]))
+    m = {k: sum(v) / len(v) for k, v in vals.items()}
+    quad = 1024 * m["GRBM_GUI_ACTIVE"] / 8 / 4
+    steps = 0.5 * n_ions * (n_ions - 1) / 64          # wave steps of 64 unique pairs
+    return {"source_sha256": kernel_sources_hash(), "n_ions": n_ions, "kernel": kernel,
+            "valu_issue_frac": (m["SQ_ACTIVE_INST_VALU"] - m["SQ_ACTIVE_INST_VALU2"]) / quad,
+            "valu_per_wave_step": m["SQ_INSTS_VALU"] / steps,
+            "trans_per_wave_step": m.get("SQ_INSTS_VALU_TRANS_F32", 0.0) / steps,
+            "dual_issue_quads_per_wave_step": m["SQ_ACTIVE_INST_VALU2"] / steps,
+            "counters": m}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--fetch", required=True)
-    ap.add_argument("--write", required=True)
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--issue", help="SQ/GRBM counter CSV of the pair kernel (issue accounting)")
     ap.add_argument("--n-ions", type=int, required=True)
     ap.add_argument("--json", required=True)
     ap.add_argument("--md")
     ap.add_argument("--command", default="")
     a = ap.parse_args(argv)
+    if a.issue:
+        s = summarise_issue(a.issue, a.n_ions)
+        s["command"] = a.command
+        with open(a.json, "w") as fh:
+            json.dump(s, fh, indent=1)
+        return
     s = summarise(a.fetch, a.write, a.n_ions)
     s["command"] = a.command
     with open(a.json, "w") as fh:

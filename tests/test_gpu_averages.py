@@ -130,3 +130,30 @@ def test_free_running_time_averages(B):
     for p in (0, 3):
         verdicts.append(_compare(names[p], [f[0, p] for f in gF], [f[0, p] for f in oF]))
     assert "FAIL" not in verdicts, verdicts
+
+
+def test_history_is_the_per_step_record(B):
+    """od_set_history / od_get_history: the device records of q(n) and the
+    four force parts equal what od_get_dust_charges / od_get_dust_forces
+    report after each step, and their mean from n_discard on equals the
+    running averages."""
+    w = W.two_grain_wake().with_(n_ions=3000, n_discard=7)
+    with B.System(w) as s:
+        s.step(3)                       # history starts at the current step
+        s.set_history(40)
+        q_before, F_step = [], []
+        for n in range(25):
+            q_before.append(s.get_state()[2])
+            s.step(1)
+            F_step.append(s.forces(0))
+        h = s.history()
+        _, q_avg = s.charges()
+        F_avg = s.forces(1)
+    assert h.shape == (25, 2, 14)
+    for k in range(25):
+        assert np.array_equal(h[k, :, 0], q_before[k]), k
+        assert np.array_equal(h[k, :, 1:13].reshape(2, 4, 3), F_step[k]), k
+    # steps 3..27 recorded; averages run over steps >= 7, i.e. records 4..24
+    assert np.allclose(h[4:, :, 0].mean(axis=0), q_avg, rtol=1e-12, atol=0)
+    assert np.allclose(h[4:, :, 1:13].mean(axis=0).reshape(2, 4, 3), F_avg, rtol=1e-12,
+                       atol=1e-12 * np.abs(F_avg).max())

@@ -142,3 +142,32 @@ def test_adam_steps_match_fp64_reference(B):
     rel = np.linalg.norm(d_gpu - d_ref) / np.linalg.norm(d_ref)
     say("adam step 1 vs FP64 gradients, relative L2 of the update difference", rel)
     assert rel < 1e-2
+
+
+def test_surrogate_train_and_predict_calls(B):
+    # the two-call surrogate interface: standardised by the data, trained,
+    # and predicting as od_mlp_predict does
+    import ctypes as C
+    L = B._mlp_lib()
+    rng = np.random.default_rng(12)
+    X = rng.uniform(-1, 1, size=(512, 5)).astype(np.float32)
+    Y = (np.sin(X @ rng.normal(size=(5, 16))) * 3.0 + 5.0).astype(np.float32)
+    lo, hi = -np.ones(5, dtype=np.float32), np.ones(5, dtype=np.float32)
+    cfg = B.TrainCfg(60, 64, 3e-3, 1e-4, 1)
+    h = C.c_void_p()
+    fp = C.POINTER(C.c_float)
+    B._check(L.od_surrogate_train(X.ctypes.data_as(fp), Y.ctypes.data_as(fp), 512, lo.ctypes.data_as(fp),
+                                  hi.ctypes.data_as(fp), C.byref(cfg), 3, None, C.byref(h)))
+    try:
+        Yp = np.zeros((512, 16), dtype=np.float32)
+        ins = np.zeros(512, dtype=np.int32)
+        B._check(L.od_surrogate_predict(h, X.ctypes.data_as(fp), 512, Yp.ctypes.data_as(fp),
+                                        ins.ctypes.data_as(C.POINTER(C.c_int32))))
+        Yq = np.zeros((512, 16), dtype=np.float32)
+        B._check(L.od_mlp_predict(h, X.ctypes.data_as(fp), 512, Yq.ctypes.data_as(fp), None))
+        assert np.array_equal(Yp, Yq) and ins.all()
+        err = np.sqrt(np.mean((Yp - Y) ** 2)) / Y.std()
+        say("surrogate train/predict relative rms error", err)
+        assert err < 0.5          # the mean alone gives 1
+    finally:
+        L.od_mlp_destroy(h)

@@ -89,6 +89,15 @@ def test_many_absorptions(B):
         r = shadow_step(s, o, w)
         say("  ", r)
         assert r["n_abs"][0] > 200
+        # the absorbed-ion list against the oracle's events
+        idx, by, na, ne = s.absorbed()
+        ev = o.last_step()["ev"]
+        ref = np.nonzero(ev >= 0)[0]
+        assert na == r["n_abs"][0] and ne == r["n_exit"]
+        if r["n_ambiguous_mismatch"] == 0:
+            assert np.array_equal(idx, ref) and np.array_equal(by, ev[ref])
+        idx2, _, na2, _ = s.absorbed(cap=10)
+        assert na2 == na and np.array_equal(idx2, idx[:10])
         r = shadow_step(s, o, w)
         say("  ", r)
 
