@@ -16,9 +16,18 @@ Targets are made dimensionless before training: charge by
 4 pi eps0 a k_B T_e / e (grain potential in units of k_B T_e / e) and force
 by a^2 n k_B T_e.
 
-Command line (GPU):
+Every run uses the paper's boundary model (Section 2, Appendix A): ions are
+injected from the stationary distribution of the field-driven collisional
+flow and feel the confinement field of the outer plasma.
+
+Command line (GPU, DIR a scratch directory):
+    python -m paper_2205_06557_amd.surrogate dtcheck --out DIR
     python -m paper_2205_06557_amd.surrogate generate --out DIR --tag train --start 0 --count 512
-    python -m paper_2205_06557_amd.surrogate evaluate --data DIR --out DIR
+    python -m paper_2205_06557_amd.surrogate generate --out DIR --tag testa --total 64 --seed 12 --run-seed 13
+    python -m paper_2205_06557_amd.surrogate pack --data DIR --out FILE.npz
+    python -m paper_2205_06557_amd.surrogate evaluate --dataset FILE.npz --out DIR
+    python -m paper_2205_06557_amd.surrogate trace --dataset FILE.npz --start surrogate --n-ions N --steps S --out F.npz
+    python -m paper_2205_06557_amd.surrogate warmstart --traces F1.npz F2.npz ... --out DIR
 """
 from __future__ import annotations
 
@@ -26,7 +35,6 @@ import argparse
 import json
 import math
 import os
-import sys
 import time
 from typing import Optional, Sequence
 
@@ -48,19 +56,29 @@ def sweep_inputs(n: int, seed: int, lo=BOX_LO, hi=BOX_HI) -> np.ndarray:
     return lo + (hi - lo) * rng.uniform(0.0, 1.0, size=(n, 5))
 
 
-DT_WPI = 0.04      # time step of the surrogate protocol, units of 1/omega_pi
-AVG_STEPS = 2000   # trailing steps averaged for the targets
+DT_WPI = 0.01      # time step of the surrogate protocol (the configurations' dt), units of 1/omega_pi
+AVG_STEPS = 2000   # trailing steps averaged for the targets (chain_workload's default)
+# Self-consistent charge of a chain grain over the isolated grain's OML floating
+# charge: 0.58 on average (spread 0.07) over the 16 inputs of the time-step
+# check at dt = 0.01/omega_pi; the training and reference runs start there.
+CHAIN_OML_RATIO = 0.58
+FLAGS = W.FLAG_FIELD_DRIVEN | W.FLAG_CONFINEMENT
+BLOCK = 200        # steps per block mean in the convergence rule
+BAND = 0.02        # relative charge band of the convergence rule
+REF_LAST = 8000    # trailing steps of the reference run that give the converged charge
+DATASET = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "chain8_N16384.npz")
+STUDY_X = (1.0, 5.0, 0.4, 0.1, 33.3)   # the chain of the warm-start study (0.4 r_De spacing, Mach 1)
 
 
 def chain_workload(x5: Sequence[float], n_ions: int, steps: int, seed: int, system_id: int,
                    q0: Optional[Sequence[float]] = None, n_discard: Optional[int] = None,
-                   dt_wpi: float = DT_WPI, avg_steps: int = AVG_STEPS) -> W.Workload:
+                   dt_wpi: float = DT_WPI, avg_steps: int = AVG_STEPS, flags: int = FLAGS) -> W.Workload:
     """The 8-grain vertical chain for one input point: grains of radius a on the
     axis at z_k = (k - 3.5) d, cylinder R = 3 r_De, H = 7 d + 5 r_De, argon at
     T_e = 1 eV, n = 1e14 m^-3, self-consistent charging, dt = dt_wpi/omega_pi
-    (0.04 by default: the grain charging time is ~70/omega_pi, so a 6,000-step
-    run spans ~3.4 charging times).  q0: initial charges (C), default 0;
-    n_discard: default steps - avg_steps."""
+    (0.01 by default, the configurations' time step; the grain charging time
+    is 40-200/omega_pi over the input box), the paper's boundary model by default.
+    q0: initial charges (C), default 0; n_discard: default steps - avg_steps."""
     mach, a_um, d_l, nu_w, tt = (float(v) for v in x5)
     te = W.ev_to_kelvin(TE_EV)
     lam = W.debye_length(te, N_INF)
@@ -73,9 +91,8 @@ def chain_workload(x5: Sequence[float], n_ions: int, steps: int, seed: int, syst
                       E_ext=float("nan"), R=3 * lam, H=7 * d + 5 * lam, dt=dt_wpi / wpi,
                       n_ions=int(n_ions), n_steps=int(steps),
                       n_discard=int(max(steps - avg_steps, 0) if n_discard is None else n_discard),
-                      seed=seed,
-                      system_id=system_id, charge_mode=W.CHARGE_CONSISTENT, dust=dust,
-                      name=f"chain8 {x5}")
+                      seed=seed, system_id=system_id, charge_mode=W.CHARGE_CONSISTENT, dust=dust,
+                      flags=int(flags), name=f"chain8 {list(map(float, x5))}")
 
 
 def charge_scale(x5) -> float:
@@ -106,13 +123,15 @@ def oml_charge(x5) -> float:
     return B.oml_floating_charge(w, float(x5[1]) * 1e-6)
 
 
-def run_plain(X: np.ndarray, n_ions: int, steps: int, seed: int, start: str = "oml",
+def run_plain(X: np.ndarray, n_ions: int, steps: int, seed: int, start: str = "ratio",
               q0: Optional[np.ndarray] = None, batch_size: int = 512, graph: int = 10,
-              log=None, avg_steps: int = AVG_STEPS) -> np.ndarray:
+              log=None, avg_steps: int = AVG_STEPS, dt_wpi: float = DT_WPI, id0: int = 0) -> np.ndarray:
     """Runs the full method for every input row (batched) and returns the
     normalised targets [n, 16]: time-averaged charge and total axial force
     (Eqs. (1)-(4) summed) of each grain over the last avg_steps steps.
-    start: "oml" (isolated-grain floating charge), "zero", or "given" (q0 [n, 8] in C)."""
+    start: "ratio" (CHAIN_OML_RATIO times the isolated-grain floating charge),
+    "oml" (that charge), "zero", or "given" (q0 [n, 8] in C).
+    Row r runs on random stream (seed, id0 + r)."""
     from . import binding as B
     n = X.shape[0]
     T = np.zeros((n, 16))
@@ -120,13 +139,13 @@ def run_plain(X: np.ndarray, n_ions: int, steps: int, seed: int, start: str = "o
         rows = range(b0, min(n, b0 + batch_size))
         ws = []
         for r in rows:
-            if start == "oml":
-                q = [oml_charge(X[r])] * N_GRAINS
+            if start in ("oml", "ratio"):
+                q = [oml_charge(X[r]) * (CHAIN_OML_RATIO if start == "ratio" else 1.0)] * N_GRAINS
             elif start == "given":
                 q = list(q0[r])
             else:
                 q = None
-            ws.append(chain_workload(X[r], n_ions, steps, seed, r, q, avg_steps=avg_steps))
+            ws.append(chain_workload(X[r], n_ions, steps, seed, id0 + r, q, avg_steps=avg_steps, dt_wpi=dt_wpi))
         t0 = time.time()
         b = B.Batch(ws)
         b.autotune(None)
@@ -139,7 +158,7 @@ def run_plain(X: np.ndarray, n_ions: int, steps: int, seed: int, start: str = "o
             b.step(k)
             b.sync()
             done += k
-            if log:
+            if log and (done % 2000 == 0 or done == steps):
                 log(f"  runs {b0}..{rows[-1]}: step {done}/{steps} ({time.time() - t0:.1f} s)")
         for i, r in enumerate(rows):
             _, qa = b.charges(i)
@@ -168,6 +187,18 @@ class Surrogate:
         s.history = hist
         return s
 
+    def save(self, path: str):
+        np.savez(path, params=self.mlp.params(), mean=self.t_mean, std=self.t_std)
+
+    @classmethod
+    def load(cls, path: str):
+        from . import binding as B
+        z = np.load(path)
+        mlp = B.Mlp(0)
+        mlp.set_normalization(BOX_LO, BOX_HI, z["mean"], z["std"])
+        mlp.set_params(z["params"])
+        return cls(mlp, z["mean"], z["std"])
+
     def predict_targets(self, X):
         return self.mlp.predict(X)
 
@@ -182,7 +213,84 @@ class Surrogate:
         return Q, F, inside
 
 
-def steps_to_converge(trace: np.ndarray, q_ref: np.ndarray, block: int, tol: float) -> Optional[int]:
+# ---------------------------------------------------------------------------
+# data set: training runs and held-out inputs run on several random streams
+
+def load_dataset(path: str = DATASET) -> dict:
+    """{"X" [n, 5], "T" [n, 16], "Xh" [m, 5], "Th" [K, m, 16], meta...}."""
+    z = np.load(path)
+    d = {k: z[k] for k in z.files}
+    for k in ("n_ions", "steps", "avg_steps", "flags"):
+        d[k] = int(d[k])
+    d["dt_wpi"] = float(d["dt_wpi"])
+    return d
+
+
+def _shards(data: str, prefix: str):
+    fs = sorted(f for f in os.listdir(data) if f.startswith(prefix) and f.endswith(".npz"))
+    return [np.load(os.path.join(data, f)) for f in fs], fs
+
+
+def pack(data: str, out: str):
+    """Merges DATA/train_*.npz and the held-out runs DATA/test<stream>_*.npz
+    (the same inputs run on independent random streams) into one file."""
+    tr, _ = _shards(data, "train_")
+    X = np.concatenate([z["X"] for z in tr])
+    T = np.concatenate([z["T"] for z in tr])
+    tags = sorted({f.split("_")[0] for f in os.listdir(data) if f.startswith("test") and f.endswith(".npz")})
+    Xh, Th = None, []
+    for tag in tags:
+        zs, _ = _shards(data, tag + "_")
+        x = np.concatenate([z["X"] for z in zs])
+        assert Xh is None or np.array_equal(Xh, x), tag
+        Xh = x
+        Th.append(np.concatenate([z["T"] for z in zs]))
+    z0 = tr[0]
+    meta = {k: z0[k] for k in ("n_ions", "steps", "avg_steps", "dt_wpi", "flags")}
+    for z in tr + [z for tag in tags for z in _shards(data, tag + "_")[0]]:
+        for k in meta:
+            assert np.array_equal(z[k], meta[k]), (k, z[k], meta[k])
+    os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
+    np.savez_compressed(out, X=X, T=T, Xh=Xh, Th=np.stack(Th), **meta)
+    print(f"[surrogate] packed {len(X)} training runs and {len(Xh)} held-out inputs x {len(Th)} streams "
+          f"into {out}", flush=True)
+
+
+def _stats(a):
+    a = np.asarray(a).ravel()
+    return {"median": float(np.median(a)), "p90": float(np.percentile(a, 90)), "mean": float(a.mean())}
+
+
+def heldout_errors(P: np.ndarray, Th: np.ndarray) -> dict:
+    """Errors of predictions P [m, 16] against the held-out reference, the mean
+    of K independent runs Th [K, m, 16].  Charges relative to the reference
+    charge, forces relative to the chain's mean absolute force.  The
+    reference's own noise is the standard error of that mean (from the spread
+    of the K runs); 'rms_excess' is the rms error with that noise removed
+    (sqrt(mean err^2 - mean se^2), 0 if negative)."""
+    K = Th.shape[0]
+    ref = Th.mean(axis=0)
+    se = Th.std(axis=0, ddof=1) / math.sqrt(K)
+    fscale = np.abs(ref[:, 8:]).mean(axis=1, keepdims=True)
+    q_err = np.abs(P[:, :8] / ref[:, :8] - 1.0)
+    q_se = se[:, :8] / np.abs(ref[:, :8])
+    f_err = np.abs(P[:, 8:] - ref[:, 8:]) / fscale
+    f_se = se[:, 8:] / fscale
+
+    def excess(e, n):
+        return float(math.sqrt(max(float(np.mean(e ** 2) - np.mean(n ** 2)), 0.0)))
+    return {"streams": int(K), "inputs": int(ref.shape[0]),
+            "charge_rel_err": _stats(q_err), "charge_reference_se": _stats(q_se),
+            "charge_rms_excess": excess(q_err, q_se),
+            "force_rel_err": _stats(f_err), "force_reference_se": _stats(f_se),
+            "force_rms_excess": excess(f_err, f_se)}
+
+
+# ---------------------------------------------------------------------------
+# warm start: time to converged charge (200-step block means, 2 % band)
+
+def steps_to_converge(trace: np.ndarray, q_ref: np.ndarray, block: int = BLOCK,
+                      tol: float = BAND) -> Optional[int]:
     """First step count at which the mean charge of a block of `block` steps is
     within `tol` (relative) of q_ref for every grain; trace [steps, grains]."""
     nb = trace.shape[0] // block
@@ -193,126 +301,209 @@ def steps_to_converge(trace: np.ndarray, q_ref: np.ndarray, block: int, tol: flo
     return None
 
 
-def charge_trace(x5, n_ions: int, steps: int, seed: int, q0, every: int = 10):
-    """Charges of a single chain run, read every `every` steps and held in
-    between (the block means of the warm-start study average over them)."""
+def charge_trace(x5, n_ions: int, steps: int, seed: int, system_id: int, q0, log=None,
+                 dt_wpi: float = DT_WPI) -> dict:
+    """Per-step charges (C) of one chain run from the charges q0 (C; None: Q = 0),
+    read from the on-device history; {"q": [steps, 8], "seconds_per_step"}
+    (the first step, which includes the set-up, is not timed)."""
     from . import binding as B
-    w = chain_workload(x5, n_ions, steps, seed, 0, q0)
-    s = B.System(w)
-    tr = np.zeros((steps, N_GRAINS))
-    t0 = time.time()
-    for k in range(steps):
+    w = chain_workload(x5, n_ions, steps, seed, system_id, q0, dt_wpi=dt_wpi)
+    with B.System(w) as s:
+        s.set_history(steps)
         s.step(1)
-        tr[k] = s.charges()[0] if (k % every == 0 or k + 1 == steps) else np.nan
-        if (k + 1) % 2000 == 0:
-            print(f"[surrogate]   step {k + 1}/{steps}, {time.time() - t0:.1f} s", flush=True)
-    s.sync()
-    # fill the unsampled steps by holding the last sample (block means only)
-    last = tr[0]
-    for k in range(steps):
-        if np.isnan(tr[k, 0]):
-            tr[k] = last
-        else:
-            last = tr[k]
-    return tr, time.time() - t0
+        s.sync()
+        t0 = time.time()
+        done = 1
+        while done < steps:
+            k = min(1000, steps - done)
+            s.step(k)
+            s.sync()
+            done += k
+            if log and (done % 2000 == 0 or done == steps):
+                log(f"  step {done}/{steps} ({time.time() - t0:.1f} s)")
+        sec = (time.time() - t0) / max(steps - 1, 1)
+        q = s.history()[:, :, 0].copy()
+    assert q.shape == (steps, N_GRAINS), q.shape
+    return {"q": q, "seconds_per_step": sec}
 
+
+def start_charges(x5, start: str, sur: Optional[Surrogate] = None):
+    """Initial charges (C) of a warm-start candidate, and the seconds taken to
+    produce them: "cold" (Q = 0), "oml" (the isolated grain's floating charge
+    for every grain), "ratio" (CHAIN_OML_RATIO times it) or "surrogate" (the
+    network's prediction)."""
+    t0 = time.time()
+    if start == "cold":
+        q = np.zeros(N_GRAINS)
+    elif start in ("oml", "ratio"):
+        q = np.full(N_GRAINS, oml_charge(x5) * (CHAIN_OML_RATIO if start == "ratio" else 1.0))
+    elif start == "surrogate":
+        Q, _, inside = sur.predict(np.asarray(x5, dtype=np.float64)[None, :])
+        if not inside[0]:
+            raise ValueError("input outside the surrogate's box: run the full method")
+        q = Q[0]
+    else:
+        raise ValueError(start)
+    return q, time.time() - t0
+
+
+def warm_start_report(ref: dict, cands: dict, block: int = BLOCK, band: float = BAND) -> dict:
+    """Time to converged charge of each candidate start against an independent
+    reference run.  ref: charge_trace of a run from its own random stream,
+    Q_ref = the mean of its last REF_LAST steps; cands: name -> charge_trace
+    plus "q0" and "start_seconds".  A candidate has converged at the first
+    block of `block` steps whose mean charge is within `band` of Q_ref for
+    every grain; its wall time is those steps times its seconds per step, plus
+    the time to make its start."""
+    qr = ref["q"]
+    q_ref = qr[-REF_LAST:].mean(axis=0)
+    half = REF_LAST // 2
+    drift = float(np.max(np.abs(qr[-REF_LAST:-half].mean(axis=0) / qr[-half:].mean(axis=0) - 1.0)))
+    out = {"q_ref_e": (q_ref / W.QE).tolist(), "reference_steps": int(len(qr)),
+           "reference_last_steps": REF_LAST, "reference_half_window_drift": drift,
+           "block_steps": block, "band": band}
+    for name, c in cands.items():
+        tr = c["q"]
+        n2 = steps_to_converge(tr, q_ref, block, band)
+        r = {"initial_max_rel_err": float(np.max(np.abs(c["q0"] / q_ref - 1.0))),
+             "steps_to_5pct": steps_to_converge(tr, q_ref, block, 0.05),
+             "steps_to_3pct": steps_to_converge(tr, q_ref, block, 0.03),
+             "steps_to_band": n2, "steps_run": int(len(tr)),
+             "seconds_per_step": c["seconds_per_step"], "start_seconds": c["start_seconds"],
+             "block_max_rel_err": [float(np.max(np.abs(tr[k:k + block].mean(axis=0) / q_ref - 1.0)))
+                                   for k in range(0, len(tr) - block + 1, block)]}
+        r["seconds_to_band"] = None if n2 is None else n2 * c["seconds_per_step"] + c["start_seconds"]
+        out[name] = r
+    cold, sur = out.get("cold"), out.get("surrogate")
+    if cold and sur and sur["seconds_to_band"] is not None:
+        if cold["seconds_to_band"] is not None:
+            out["speedup_vs_cold"] = cold["seconds_to_band"] / sur["seconds_to_band"]
+        else:   # cold start not converged within its run: a lower bound
+            out["speedup_vs_cold_at_least"] = (cold["steps_run"] * cold["seconds_per_step"]
+                                               / sur["seconds_to_band"])
+    return out
+
+
+def warm_start_study(x5, n_ions: int, ref_steps: int, steps: int, sur: Surrogate, seed: int = 4,
+                     starts=("cold", "oml", "surrogate"), log=None) -> dict:
+    """The whole study in one process: the reference run (started at
+    CHAIN_OML_RATIO times the OML charge, random stream (seed, 1)) and each
+    candidate (stream (seed, 0), common to all candidates), then
+    warm_start_report."""
+    if log:
+        log(f"[surrogate] warm start, N={n_ions}: reference run ({ref_steps} steps)")
+    q0, _ = start_charges(x5, "ratio")
+    ref = charge_trace(x5, n_ions, ref_steps, seed, 1, q0, log=log)
+    cands = {}
+    for name in starts:
+        if log:
+            log(f"[surrogate] warm start: {name} ({steps} steps)")
+        q0, t = start_charges(x5, name, sur)
+        c = charge_trace(x5, n_ions, steps, seed, 0, q0, log=log)
+        c.update(q0=q0, start_seconds=t)
+        cands[name] = c
+    rep = warm_start_report(ref, cands)
+    rep.update(x=list(map(float, x5)), n_ions=int(n_ions))
+    return rep
+
+
+# ---------------------------------------------------------------------------
+# command-line steps
 
 def generate(out: str, tag: str, total: int, start: int, count: int, n_ions: int, steps: int,
-             seed: int, run_seed: int, avg_steps: int = AVG_STEPS):
+             seed: int, run_seed: int, avg_steps: int = AVG_STEPS, dt_wpi: float = DT_WPI):
     """Rows [start, start + count) of the sweep of `total` inputs (stream `seed`),
-    run with the full method (random stream `run_seed`); saved as DIR/TAG_START.npz."""
+    run with the full method (random streams (run_seed, row)); saved as DIR/TAG_START.npz."""
     os.makedirs(out, exist_ok=True)
     X = sweep_inputs(total, seed)[start:start + count]
     t0 = time.time()
-    print(f"[surrogate] {tag}: rows {start}..{start + count - 1}, N={n_ions}, {steps} steps, "
-          f"averages over the last {avg_steps}", flush=True)
-    T = run_plain(X, n_ions, steps, seed=run_seed, log=lambda m: print(m, flush=True), avg_steps=avg_steps)
+    print(f"[surrogate] {tag}: rows {start}..{start + len(X) - 1}, N={n_ions}, {steps} steps at dt "
+          f"{dt_wpi}/omega_pi, averages over the last {avg_steps}", flush=True)
+    T = run_plain(X, n_ions, steps, seed=run_seed, log=lambda m: print(m, flush=True), avg_steps=avg_steps,
+                  dt_wpi=dt_wpi, id0=start)
     np.savez(os.path.join(out, f"{tag}_{start:05d}.npz"), X=X, T=T, n_ions=n_ions, steps=steps,
-             avg_steps=avg_steps, seconds=time.time() - t0)
+             avg_steps=avg_steps, dt_wpi=dt_wpi, flags=FLAGS, seconds=time.time() - t0)
     print(f"[surrogate] {tag}: done in {time.time() - t0:.1f} s", flush=True)
 
 
-def _load(data: str, tag: str, with_meta: bool = False):
-    fs = sorted(f for f in os.listdir(data) if f.startswith(tag + "_") and f.endswith(".npz"))
-    Xs, Ts, meta = [], [], {}
-    for f in fs:
-        z = np.load(os.path.join(data, f))
-        Xs.append(z["X"])
-        Ts.append(z["T"])
-        meta = {"n_ions": int(z["n_ions"]), "steps": int(z["steps"]),
-                "avg_steps": int(z["avg_steps"]) if "avg_steps" in z.files else AVG_STEPS}
-    X, T = np.concatenate(Xs), np.concatenate(Ts)
-    return (X, T, meta) if with_meta else (X, T)
-
-
-def evaluate(data: str, out: str, epochs: int, eval_ions: int, eval_steps: int, seed: int = 11):
-    """Trains on DATA/train_*.npz, compares with DATA/testa_*.npz and
-    DATA/testb_*.npz (the same held-out inputs, two random streams), and runs
-    the warm-start study; writes OUT/surrogate_result.json."""
+def dtcheck(out: str, n_inputs: int = 16, n_ions: int = 1 << 14, run_wpi: float = 400.0,
+            avg_wpi: float = 240.0, dts=(0.04, 0.02, 0.01), seed: int = 21, run_seed: int = 22):
+    """Convergence of the targets in the time step: the same inputs run at each
+    dt for the same physical time (run_wpi/omega_pi, averaged over the last
+    avg_wpi/omega_pi, charges started at the OML value), each input on two
+    independent random streams.  For each
+    dt against the smallest one it reports the rms difference of the targets
+    and the rms noise that the two streams' spread predicts for that
+    difference; their excess is the systematic effect of the time step."""
     os.makedirs(out, exist_ok=True)
+    X = sweep_inputs(n_inputs, seed)
+    X2 = np.concatenate([X, X])
+    Ts = {}
+    for dt in dts:
+        steps = int(round(run_wpi / dt))
+        avg = int(round(avg_wpi / dt))
+        t0 = time.time()
+        print(f"[surrogate] dt check: dt {dt}/omega_pi, {steps} steps, {len(X2)} runs", flush=True)
+        Ts[dt] = run_plain(X2, n_ions, steps, run_seed, start="oml", batch_size=len(X2), avg_steps=avg,
+                           dt_wpi=dt, log=lambda m: print(m, flush=True))
+        print(f"[surrogate] dt check: dt {dt} done in {time.time() - t0:.1f} s", flush=True)
+    np.savez(os.path.join(out, "dtcheck.npz"), X=X, dts=np.array(dts),
+             T=np.stack([Ts[dt] for dt in dts]), n_ions=n_ions, run_wpi=run_wpi, avg_wpi=avg_wpi)
+    res = dtcheck_report(X, dts, [Ts[dt] for dt in dts])
+    res.update(n_ions=n_ions, run_wpi=run_wpi, avg_wpi=avg_wpi)
+    with open(os.path.join(out, "dtcheck.json"), "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(res), flush=True)
+    return res
 
-    def log(m):
-        print(m, flush=True)
 
-    X, T, meta = _load(data, "train", with_meta=True)
-    Xt, Ta = _load(data, "testa")
-    Xt2, Tb = _load(data, "testb")
-    assert np.array_equal(Xt, Xt2)
-    res = {"train_rows": int(len(X)), "test_rows": int(len(Xt)), "dt_wpi": DT_WPI,
-           "run_n_ions": meta["n_ions"], "run_steps": meta["steps"], "avg_steps": meta["avg_steps"]}
+def dtcheck_report(X, dts, Ts) -> dict:
+    """Ts[i]: targets [2n, 16] at dts[i], rows n.. the second stream of rows ..n."""
+    n = len(X)
+    i0 = int(np.argmin(dts))
+    a0, b0 = Ts[i0][:n], Ts[i0][n:]
+    m0 = 0.5 * (a0 + b0)
+    qs = np.abs(m0[:, :8])
+    fs = np.abs(m0[:, 8:]).mean(axis=1, keepdims=True)
+    res = {"reference_dt": float(dts[i0]), "inputs": n, "per_dt": {}}
+    for i, dt in enumerate(dts):
+        a, b = Ts[i][:n], Ts[i][n:]
+        m = 0.5 * (a + b)
+        for part, sl, sc in (("charge", slice(0, 8), qs), ("force", slice(8, 16), fs)):
+            d = (m[:, sl] - m0[:, sl]) / sc
+            # variance of a two-run mean from the two runs: (a - b)^2 / 4
+            v = ((a[:, sl] - b[:, sl]) ** 2 / 4 + (a0[:, sl] - b0[:, sl]) ** 2 / 4) / sc ** 2
+            rms_d = float(np.sqrt(np.mean(d ** 2)))
+            rms_n = float(np.sqrt(np.mean(v))) if i != i0 else 0.0
+            res["per_dt"].setdefault(str(dt), {})[part] = {
+                "rms_rel_diff": rms_d, "rms_rel_noise_of_diff": rms_n,
+                "systematic_rms": float(math.sqrt(max(rms_d ** 2 - rms_n ** 2, 0.0))),
+                "mean_rel_diff": float(d.mean()),
+                "mean_rel_diff_se": float(d.std(ddof=1) / math.sqrt(d.size)),
+                "run_noise_rms": float(np.sqrt(np.mean((a[:, sl] - b[:, sl]) ** 2 / 2 / sc ** 2)))}
+    return res
+
+
+def evaluate(dataset: str, out: str, epochs: int, seed: int = 11) -> dict:
+    """Trains on the data set's training runs and measures the errors on its
+    held-out inputs; writes OUT/surrogate_result.json and the network."""
+    os.makedirs(out, exist_ok=True)
+    d = load_dataset(dataset)
+    res = {"train_rows": int(len(d["X"])), "dt_wpi": d["dt_wpi"], "flags": d["flags"],
+           "run_n_ions": d["n_ions"], "run_steps": d["steps"], "avg_steps": d["avg_steps"], "epochs": epochs}
     t1 = time.time()
-    sur = Surrogate.train(X, T, epochs=epochs, seed=seed)
+    sur = Surrogate.train(d["X"], d["T"], epochs=epochs, seed=seed)
     res["train_s"] = time.time() - t1
     res["loss_first_last"] = [float(sur.history[0]), float(sur.history[-1])]
-    np.save(os.path.join(out, "params.npy"), sur.mlp.params())
-    np.savez(os.path.join(out, "norm.npz"), mean=sur.t_mean, std=sur.t_std)
+    sur.save(os.path.join(out, "network.npz"))
     t2 = time.time()
-    P, inside = sur.predict_targets(Xt)
-    res["predict_s_per_point"] = (time.time() - t2) / len(Xt)
-    ref = 0.5 * (Ta + Tb)
-    q_err = np.abs(P[:, :8] / ref[:, :8] - 1.0)
-    q_noise = np.abs(Ta[:, :8] / Tb[:, :8] - 1.0) / math.sqrt(2)
-    fscale = np.abs(ref[:, 8:]).mean(axis=1, keepdims=True)
-    f_err = np.abs(P[:, 8:] - ref[:, 8:]) / fscale
-    f_noise = np.abs(Ta[:, 8:] - Tb[:, 8:]) / fscale / math.sqrt(2)
-
-    def st(a):
-        return {"median": float(np.median(a)), "p90": float(np.percentile(a, 90)), "mean": float(a.mean())}
-    res["charge_rel_err"] = st(q_err)
-    res["charge_noise_of_reference"] = st(q_noise)
-    res["force_rel_err_vs_mean_abs"] = st(f_err)
-    res["force_noise_of_reference"] = st(f_noise)
+    P, inside = sur.predict_targets(d["Xh"])
+    res["predict_s_per_point"] = (time.time() - t2) / len(d["Xh"])
     res["inside_box"] = int(inside.sum())
-    # warm start vs cold start on one chain at a larger N
-    x5 = np.array([1.0, 5.0, 0.4, 0.1, 33.3])
-    Qp, Fp, _ = sur.predict(x5[None, :])
-    q_oml = oml_charge(x5)
-    log("[surrogate] warm-start study: reference run")
-    ref_tr, ref_s = charge_trace(x5, eval_ions, eval_steps, seed + 5, Qp[0])
-    q_ref = ref_tr[-eval_steps // 2:].mean(axis=0)
-    ws = {"x": x5.tolist(), "n_ions": eval_ions, "steps": eval_steps, "q_ref_e": (q_ref / W.QE).tolist(),
-          "surrogate_q_e": (Qp[0] / W.QE).tolist(), "oml_q_e": q_oml / W.QE,
-          "surrogate_q_err_vs_ref": float(np.max(np.abs(Qp[0] / q_ref - 1))),
-          "reference_seconds": ref_s}
-    for name, q0 in (("cold", np.zeros(8)), ("oml", np.full(8, q_oml)), ("surrogate", Qp[0])):
-        log(f"[surrogate] warm-start study: {name}")
-        tr, secs = charge_trace(x5, eval_ions, eval_steps, seed + 6, q0)
-        win = 500
-        errs = [float(np.max(np.abs(tr[k:k + win].mean(axis=0) / q_ref - 1.0)))
-                for k in range(0, eval_steps - win + 1, win)]
-        ws[name] = {"initial_max_rel_err": float(np.max(np.abs(q0 / q_ref - 1.0))),
-                    "window_steps": win, "window_max_rel_err": errs,
-                    "steps_to_5pct": steps_to_converge(tr, q_ref, win, 0.05),
-                    "steps_to_3pct": steps_to_converge(tr, q_ref, win, 0.03),
-                    "seconds_per_step": secs / eval_steps}
-    t3 = time.time()
-    for _ in range(100):
-        sur.predict(x5[None, :])
-    ws["surrogate_seconds_per_eval"] = (time.time() - t3) / 100
-    res["warm_start"] = ws
+    res["heldout"] = heldout_errors(P, d["Th"])
     with open(os.path.join(out, "surrogate_result.json"), "w") as f:
         json.dump(res, f, indent=1)
-    log(json.dumps(res))
+    print(json.dumps(res), flush=True)
     return res
 
 
@@ -322,26 +513,83 @@ def main(argv=None):
     g = sub.add_parser("generate")
     g.add_argument("--out", required=True)
     g.add_argument("--tag", default="train")
-    g.add_argument("--total", type=int, default=1024)
+    g.add_argument("--total", type=int, default=2048)
     g.add_argument("--start", type=int, default=0)
     g.add_argument("--count", type=int, default=512)
     g.add_argument("--n-ions", type=int, default=1 << 14)
-    g.add_argument("--steps", type=int, default=6000)
+    g.add_argument("--steps", type=int, default=30000)
+    g.add_argument("--avg-steps", type=int, default=15000)
+    g.add_argument("--dt", type=float, default=DT_WPI)
     g.add_argument("--seed", type=int, default=11)
     g.add_argument("--run-seed", type=int, default=11)
-    g.add_argument("--avg-steps", type=int, default=AVG_STEPS)
+    c = sub.add_parser("dtcheck")
+    c.add_argument("--out", required=True)
+    c.add_argument("--inputs", type=int, default=16)
+    c.add_argument("--n-ions", type=int, default=1 << 14)
+    p = sub.add_parser("pack")
+    p.add_argument("--data", required=True)
+    p.add_argument("--out", default=DATASET)
     e = sub.add_parser("evaluate")
-    e.add_argument("--data", required=True)
+    e.add_argument("--dataset", default=DATASET)
     e.add_argument("--out", required=True)
     e.add_argument("--epochs", type=int, default=600)
-    e.add_argument("--eval-ions", type=int, default=1 << 16)
-    e.add_argument("--eval-steps", type=int, default=10000)
+    t = sub.add_parser("trace")
+    t.add_argument("--dataset", default=DATASET)
+    t.add_argument("--network", default=None, help="saved network (default: train on the data set)")
+    t.add_argument("--epochs", type=int, default=600)
+    t.add_argument("--start", choices=("reference", "cold", "oml", "ratio", "surrogate"), required=True)
+    t.add_argument("--x", default=",".join(map(str, STUDY_X)))
+    t.add_argument("--n-ions", type=int, default=1 << 19)
+    t.add_argument("--steps", type=int, required=True)
+    t.add_argument("--seed", type=int, default=4)
+    t.add_argument("--out", required=True)
+    r = sub.add_parser("warmstart")
+    r.add_argument("--traces", nargs="+", required=True)
+    r.add_argument("--out", required=True)
     a = ap.parse_args(argv)
+    log = lambda m: print(m, flush=True)   # noqa: E731
     if a.cmd == "generate":
         generate(a.out, a.tag, a.total, a.start, a.count, a.n_ions, a.steps, a.seed, a.run_seed,
-                 a.avg_steps)
+                 a.avg_steps, a.dt)
+    elif a.cmd == "dtcheck":
+        dtcheck(a.out, a.inputs, a.n_ions)
+    elif a.cmd == "pack":
+        pack(a.data, a.out)
+    elif a.cmd == "evaluate":
+        evaluate(a.dataset, a.out, a.epochs)
+    elif a.cmd == "trace":
+        x5 = np.array([float(v) for v in a.x.split(",")])
+        sur = None
+        if a.start == "surrogate":
+            if a.network:
+                sur = Surrogate.load(a.network)
+            else:
+                d = load_dataset(a.dataset)
+                sur = Surrogate.train(d["X"], d["T"], epochs=a.epochs, seed=11)
+        name = "ratio" if a.start == "reference" else a.start
+        q0, t0 = start_charges(x5, name, sur)
+        sysid = 1 if a.start == "reference" else 0
+        log(f"[surrogate] trace {a.start}: N={a.n_ions}, {a.steps} steps, stream ({a.seed}, {sysid})")
+        c = charge_trace(x5, a.n_ions, a.steps, a.seed, sysid, q0, log=log)
+        np.savez(a.out, start=a.start, q=c["q"], q0=q0, start_seconds=t0,
+                 seconds_per_step=c["seconds_per_step"], x=x5, n_ions=a.n_ions)
     else:
-        evaluate(a.data, a.out, a.epochs, a.eval_ions, a.eval_steps)
+        ref, cands, meta = None, {}, {}
+        for f in a.traces:
+            z = np.load(f)
+            c = {"q": z["q"], "q0": z["q0"], "start_seconds": float(z["start_seconds"]),
+                 "seconds_per_step": float(z["seconds_per_step"])}
+            meta = {"x": z["x"].tolist(), "n_ions": int(z["n_ions"])}
+            if str(z["start"]) == "reference":
+                ref = c
+            else:
+                cands[str(z["start"])] = c
+        rep = warm_start_report(ref, cands)
+        rep.update(meta)
+        os.makedirs(a.out, exist_ok=True)
+        with open(os.path.join(a.out, "warm_start.json"), "w") as f:
+            json.dump(rep, f, indent=1)
+        print(json.dumps(rep), flush=True)
 
 
 if __name__ == "__main__":

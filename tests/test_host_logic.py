@@ -55,6 +55,8 @@ def test_chain_geometry():
     assert w.nu_in / w.wpi == pytest.approx(0.1)
     assert w.dt * w.wpi == pytest.approx(S.DT_WPI)
     assert w.n_discard == 6000 - S.AVG_STEPS
+    # the paper's boundary model (Section 2, Appendix A)
+    assert w.flags == W.FLAG_FIELD_DRIVEN | W.FLAG_CONFINEMENT
     # every grain inside the domain, away from the walls
     for (_, _, zz, a, _) in w.dust:
         assert abs(zz) + a < 0.5 * w.H - 2 * lam
@@ -92,3 +94,64 @@ def test_pmc_summary_maps_the_symmetric_pair_kernels(tmp_path):
     assert s["kernels"]["pair"]["fetch_bytes"] == pytest.approx(4000.0 * 1024 / 0.5)
     assert s["kernels"]["pair"]["write_bytes"] == pytest.approx(9000.0 * 1024)
     assert s["kernels"]["tail"]["traffic_bytes"] == pytest.approx((30.0 / 0.5 + 20.0) * 1024)
+
+
+def test_warm_start_report_rule():
+    """The convergence rule on synthetic traces: 200-step block means, every
+    grain within 2 % of the reference's trailing mean."""
+    rng = np.random.default_rng(0)
+    q_ref = -np.linspace(900.0, 1300.0, 8) * 1.602e-19
+    ref = {"q": q_ref * (1 + 0.003 * rng.standard_normal((6000, 8)))}
+    t = np.arange(4000)[:, None]
+    cold = q_ref * (1 - np.exp(-t / 500.0))
+    sur = np.tile(q_ref * 1.01, (4000, 1))
+    late = np.tile(q_ref * 1.5, (4000, 1))            # never converges
+    cands = {"cold": {"q": cold, "q0": cold[0], "seconds_per_step": 2e-3, "start_seconds": 0.0},
+             "surrogate": {"q": sur, "q0": sur[0], "seconds_per_step": 2e-3, "start_seconds": 1e-4},
+             "oml": {"q": late, "q0": late[0], "seconds_per_step": 2e-3, "start_seconds": 0.0}}
+    r = S.warm_start_report(ref, cands)
+    assert np.allclose(np.array(r["q_ref_e"]) * W.QE, q_ref, rtol=2e-3)
+    assert r["surrogate"]["steps_to_band"] == 200
+    assert r["oml"]["steps_to_band"] is None
+    n = r["cold"]["steps_to_band"]
+    assert n % 200 == 0
+    # the block that converges is inside the band, the one before it is not
+    errs = r["cold"]["block_max_rel_err"]
+    assert errs[n // 200 - 1] <= 0.02 < errs[n // 200 - 2]
+    assert r["speedup_vs_cold"] == pytest.approx((n * 2e-3) / (200 * 2e-3 + 1e-4))
+    assert r["surrogate"]["initial_max_rel_err"] == pytest.approx(0.01, rel=0.3)
+
+
+def test_heldout_errors_remove_reference_noise():
+    rng = np.random.default_rng(1)
+    m, K = 400, 4
+    truth = np.concatenate([-rng.uniform(1.0, 3.0, (m, 8)), rng.uniform(-5.0, 5.0, (m, 8))], axis=1)
+    noise = 0.02 * np.abs(truth).mean(axis=0)
+    Th = truth[None] + noise * rng.standard_normal((K, m, 16))
+    r = S.heldout_errors(truth, Th)
+    assert r["streams"] == K and r["inputs"] == m
+    assert r["charge_rms_excess"] < 0.004            # an exact prediction: only the reference's noise
+    P = truth.copy()
+    P[:, :8] *= 1.05
+    r = S.heldout_errors(P, Th)
+    assert r["charge_rel_err"]["median"] == pytest.approx(0.05, abs=0.01)
+    assert r["charge_rms_excess"] == pytest.approx(0.05, abs=0.005)
+
+
+def test_dtcheck_report_finds_a_time_step_bias():
+    rng = np.random.default_rng(2)
+    n = 300
+    X = S.sweep_inputs(n, 1)
+    base = np.concatenate([-rng.uniform(1.0, 3.0, (n, 8)), rng.uniform(1.0, 5.0, (n, 8))], axis=1)
+    dts = (0.04, 0.02, 0.01)
+    Ts = []
+    for dt in dts:
+        bias = 1.0 + 2.0 * (dt - 0.01)                # 6 % at 0.04, 2 % at 0.02
+        Ts.append(np.concatenate([base * bias, base * bias]) * (1 + 0.01 * rng.standard_normal((2 * n, 16))))
+    r = S.dtcheck_report(X, dts, Ts)
+    assert r["reference_dt"] == 0.01
+    c04 = r["per_dt"]["0.04"]["charge"]
+    assert c04["systematic_rms"] == pytest.approx(0.06, rel=0.1)
+    assert c04["mean_rel_diff"] == pytest.approx(-0.06, rel=0.1)     # charges are negative
+    assert r["per_dt"]["0.02"]["charge"]["systematic_rms"] == pytest.approx(0.02, rel=0.2)
+    assert r["per_dt"]["0.01"]["charge"]["rms_rel_diff"] == 0.0
