@@ -366,9 +366,23 @@ od_status od_batch_get_config(od_batch* b, int32_t* persistent, int32_t* jsplit,
 od_status od_batch_set_pair_kernel(od_batch* b, int32_t kind);
 od_status od_batch_get_pair_kernel(od_batch* b, int32_t* kind);
 
+/* Decomposition of the symmetric pair sums of the batch.  persistent: a grid
+ * of (CUs x resident blocks) pulls the work items, ordered most work first,
+ * from an atomic queue (else, the default, one block per item, which the
+ * hardware dispatches in the same order).  one_row: one target tile row per
+ * item for every system (else, the default, each system split as it is when
+ * run alone: three rows per item from 2^16 ions on).  Scheduling does not
+ * change the results (integer totals); one_row changes the FP32 partial sums
+ * that each item flushes, so a system then differs from its run alone by
+ * rounding.  Drops a captured graph; *n_items (may be NULL) is the length of
+ * the work list. */
+od_status od_batch_set_sym_config(od_batch* b, int32_t persistent, int32_t one_row);
+od_status od_batch_get_sym_config(od_batch* b, int32_t* persistent, int32_t* one_row, int32_t* n_items);
+
 /* Times the pair phase for each candidate configuration (one-sided:
- * persistent or not, jsplit 1, 2, 4, split_max_n 2^15, 2^16; and the
- * symmetric kernel), keeps the fastest, and returns its time in *best_ms.  With cache_path (a text file of one JSON object per
+ * persistent or not, jsplit 1, 2, 4, split_max_n 2^15, 2^16; symmetric:
+ * persistent or not, one target row per item or the size rule), keeps the
+ * fastest, and returns its time in *best_ms.  With cache_path (a text file of one JSON object per
  * line, keyed by GPU architecture, CU count and the histogram of log2 N of
  * the systems) a cached choice is reused and a new one appended.  The
  * systems' state is unchanged. */

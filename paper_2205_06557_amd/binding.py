@@ -375,12 +375,16 @@ def _batch_lib():
                                                C.POINTER(C.c_int32)]
         L.od_batch_set_pair_kernel.argtypes = [vp, i32]
         L.od_batch_get_pair_kernel.argtypes = [vp, C.POINTER(C.c_int32)]
+        L.od_batch_set_sym_config.argtypes = [vp, i32, i32]
+        L.od_batch_get_sym_config.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                              C.POINTER(C.c_int32)]
         for name in ("od_init_batch", "od_batch_set_config", "od_batch_get_config", "od_batch_autotune",
                      "od_batch_set_graph", "od_step_batch", "od_batch_sync", "od_batch_get_sizes",
                      "od_batch_get_dust_charges", "od_batch_get_dust_forces", "od_batch_get_state",
                      "od_batch_set_state", "od_batch_get_accelerations", "od_batch_get_step_events",
                      "od_batch_set_timing", "od_batch_get_kernel_times", "od_batch_get_confinement",
-                     "od_batch_set_pair_kernel", "od_batch_get_pair_kernel"):
+                     "od_batch_set_pair_kernel", "od_batch_get_pair_kernel", "od_batch_set_sym_config",
+                     "od_batch_get_sym_config"):
             getattr(L, name).restype = C.c_int
         _batch_sigs = True
     return L
@@ -502,6 +506,14 @@ class Batch:
         k = C.c_int32(0)
         _check(_batch_lib().od_batch_get_pair_kernel(self._h, C.byref(k)))
         return k.value
+
+    def set_sym_config(self, persistent: bool = False, one_row: bool = False):
+        _check(_batch_lib().od_batch_set_sym_config(self._h, 1 if persistent else 0, 1 if one_row else 0))
+
+    def sym_config(self):
+        p, r, n = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+        _check(_batch_lib().od_batch_get_sym_config(self._h, C.byref(p), C.byref(r), C.byref(n)))
+        return dict(persistent=p.value, one_row=r.value, n_items=n.value)
 
     def events(self, s: int):
         N = int(self.ws[s].n_ions)

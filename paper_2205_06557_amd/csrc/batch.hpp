@@ -80,22 +80,23 @@ void pair_batch_kernel(const float* __restrict__ xs,
 }
 
 // Symmetric pair sums of the batch (each unordered pair once, see
-// pairsym.hpp): item = (system, target tile row, source tile run); int64
+// pairsym.hpp): item = (system, target tile rows, source tile run); int64
 // fixed-point totals in fix (planes `plane` apart, system at its offset).
+// The items are ordered most work first.  persistent != 0: a grid of about
+// one resident wave of blocks pulls items from bc->queue (the longest-first
+// greedy schedule, taken by whichever block frees up first) until the list is
+// exhausted; else block b does item b and the hardware dispatcher hands out
+// blocks in index order.  The totals are integers, so both give the same sums.
 struct SymBatchItem {
     int sys, I, J0, J1, rows, st0, st1, pad_;
 };
 
-template <int BLOCK, int TJ>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(kSymWaves, 8)))
-void pair_sym_batch_kernel(const float* __restrict__ xs, long long plane, const SysDesc* sys,
-                           Ctl* __restrict__ ctls, const SymBatchItem* __restrict__ items,
-                           unsigned long long* __restrict__ fix)
+template <int BLOCK>
+__device__ __forceinline__ void sym_batch_item(const float* __restrict__ xs, long long plane, const SysDesc* sys,
+                                               Ctl* __restrict__ ctls, const SymBatchItem& it,
+                                               unsigned long long* __restrict__ fix, float4 (*src)[128],
+                                               float (*jpart)[3][BLOCK])
 {
-    static_assert(BLOCK == TJ, "square tiles");
-    __shared__ float4 src[4][128];
-    __shared__ float jpart[4][3][BLOCK];
-    const SymBatchItem it = items[blockIdx.x];
     const int s = uniform_int(it.sys);
     const long long off = sys[s].off;
     const float* X = xs + off;
@@ -105,10 +106,34 @@ void pair_sym_batch_kernel(const float* __restrict__ xs, long long plane, const 
                         &ctls[s].status, src, jpart, PlainPair{});
 }
 
+template <int BLOCK, int TJ, bool PERSISTENT>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(kSymWaves, 8)))
+void pair_sym_batch_kernel(const float* __restrict__ xs, long long plane, const SysDesc* sys,
+                           Ctl* __restrict__ ctls, const SymBatchItem* __restrict__ items, int n_items,
+                           unsigned long long* __restrict__ fix, BatchCtl* bc)
+{
+    static_assert(BLOCK == TJ, "square tiles");
+    __shared__ float4 src[4][128];
+    __shared__ float jpart[4][3][BLOCK];
+    if (!PERSISTENT) {
+        sym_batch_item<BLOCK>(xs, plane, sys, ctls, items[blockIdx.x], fix, src, jpart);
+        return;
+    }
+    __shared__ int cur;
+    for (;;) {
+        if (threadIdx.x == 0) cur = (int)atomicAdd(&bc->queue, 1u);
+        __syncthreads();
+        const int k = uniform_int(cur);
+        __syncthreads();
+        if (k >= n_items) break;
+        sym_batch_item<BLOCK>(xs, plane, sys, ctls, items[k], fix, src, jpart);
+    }
+}
+
 // The per-ion tail of the step for every system (block b belongs to system
 // blk_sys[b]; see tail_block): FIX for the symmetric pair sums (totals in
 // fix), else the one-sided kernel's acceleration planes.  Block 0 also
-// rewinds the one-sided kernel's work queue, whose pair kernel has finished.
+// rewinds the pair kernel's work queue (that kernel has finished).
 template <bool FIX>
 __global__ __launch_bounds__(256) void step_tail_batch_kernel(float* __restrict__ xs, float* __restrict__ vs,
                                                               float* __restrict__ as, long long plane,

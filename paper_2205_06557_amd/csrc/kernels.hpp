@@ -496,14 +496,24 @@ __device__ void reinject(const PushArgs& p, uint64_t ion, uint64_t n, double o[6
 // that lost it, and, in the last block of the system to finish, the charge
 // update and force assembly.
 
-// Kick, charge exchange and drift of one ion from x with velocity v and
-// acceleration a; absorption (the earliest grain met along the drift
-// segment, ties to the lower index) and exit tests.  Returns the new x, v in
-// y, w; absorbed ions add to the grain's count and momentum.
+// Charge exchange of ion i in step n (Section 2, constant frequency): the
+// first word of block (i, n, COLL, 0) below Tc = floor(P 2^64), P = 1 - e^(-nu dt).
+// It depends on no ion data, so the step's tail evaluates it while the ion's
+// loads are in flight.
+__device__ __forceinline__ bool collision_decision(int i, uint64_t n, const PushArgs& p)
+{
+    return p.Tc != 0 && philox((uint64_t)i, n, kColl, 0, p.k0, p.k1).w[0] < p.Tc;
+}
+
+// Kick, charge exchange (collide: the decision of collision_decision) and
+// drift of one ion from x with velocity v and acceleration a; absorption (the
+// earliest grain met along the drift segment, ties to the lower index) and
+// exit tests.  Returns the new x, v in y, w; absorbed ions add to the grain's
+// count and momentum.
 template <typename T>
 __device__ __forceinline__ void push_core(const T x[3], const T v[3], const T a[3], int i, uint64_t n,
                                           const PushArgs& p, const DustSet& ds, Ctl* __restrict__ ctl,
-                                          T y[3], T w[3], uint8_t& code, bool& coll, bool& lost)
+                                          bool collide, T y[3], T w[3], uint8_t& code, bool& coll, bool& lost)
 {
 #pragma clang fp contract(off)      // the same rounding in every kernel that inlines it
     const T dt = (T)p.dt;
@@ -511,18 +521,15 @@ __device__ __forceinline__ void push_core(const T x[3], const T v[3], const T a[
     T v0 = fma(dt, a[0], v[0]);
     T v1 = fma(dt, a[1], v[1]);
     T v2 = fma(dt, a[2], v[2]);
-    if (p.Tc != 0) {
-        const U64x4 r = philox((uint64_t)i, n, kColl, 0, p.k0, p.k1);
-        if (r.w[0] < p.Tc) {
-            const U64x4 g = philox((uint64_t)i, n, kColl, 1, p.k0, p.k1);
-            double g1, g2, g3, g4;
-            gauss2(unit(g.w[0]), unit(g.w[1]), g1, g2);
-            gauss2(unit(g.w[2]), unit(g.w[3]), g3, g4);
-            v0 = (T)(p.sig * g1);
-            v1 = (T)(p.sig * g2);
-            v2 = (T)(p.sig * g3);
-            coll = true;
-        }
+    if (collide) {      // see collision_decision; the new velocity from the block after it
+        const U64x4 g = philox((uint64_t)i, n, kColl, 1, p.k0, p.k1);
+        double g1, g2, g3, g4;
+        gauss2(unit(g.w[0]), unit(g.w[1]), g1, g2);
+        gauss2(unit(g.w[2]), unit(g.w[3]), g3, g4);
+        v0 = (T)(p.sig * g1);
+        v1 = (T)(p.sig * g2);
+        v2 = (T)(p.sig * g3);
+        coll = true;
     }
     const T y0 = fma(dt, v0, x[0]), y1 = fma(dt, v1, x[1]), y2 = fma(dt, v2, x[2]);
     // Absorption: does the drift segment x -> y meet a grain?  FP64 on
@@ -581,8 +588,8 @@ __device__ __forceinline__ void push_core(const T x[3], const T v[3], const T a[
     w[0] = v0; w[1] = v1; w[2] = v2;
 }
 
-// Acceleration of ion i from the symmetric pair sum's fixed-point totals
-// fix[c * fstride + i] (cleared here), the homogeneous drive, the
+// Acceleration of an ion from the symmetric pair sum's fixed-point totals
+// fx (read by the caller), the homogeneous drive, the
 // confinement field and the bare Coulomb pull of every grain (FP32 terms of
 // FP64 differences, summed in FP64).  When `eq1` is set the ion's Eq. (1)
 // summands (1 + rho) e^-rho / rho^3 (r_d - x_i), FP32 terms, are reduced over
@@ -590,18 +597,14 @@ __device__ __forceinline__ void push_core(const T x[3], const T v[3], const T a[
 // of the wave must call it.  Floating-point contraction is off here (the only
 // fused operations are the written fmaf), so that every kernel that inlines
 // it rounds alike: a system in a batch reproduces the same system run alone.
-__device__ __forceinline__ void accel_from_fixed(const float x[3], bool live, int i,
-                                                 unsigned long long* __restrict__ fix, long long fstride,
-                                                 const PairArgs& pa, const DustSet& ds, const double* Kd,
-                                                 float a[3], double (*red)[kMaxDust][3])
+__device__ __forceinline__ void accel_from_fixed(const float x[3], bool live, const unsigned long long fx[3],
+                                                 const PairArgs& pa, const DustSet& ds,
+                                                 const double* __restrict__ Q, float a[3],
+                                                 double (*red)[kMaxDust][3])
 {
 #pragma clang fp contract(off)
     double g[3];
-    for (int c = 0; c < 3; ++c) {
-        unsigned long long* q = &fix[c * fstride + i];
-        g[c] = live ? pa.Cd * from_fixed(*q, pa.sym_scale) : 0.0;
-        *q = 0ull;
-    }
+    for (int c = 0; c < 3; ++c) g[c] = live ? pa.Cd * from_fixed(fx[c], pa.sym_scale) : 0.0;
     g[2] += pa.Ez;
     if (pa.cf.on) {
         double ex, ey, ez;
@@ -617,7 +620,7 @@ __device__ __forceinline__ void accel_from_fixed(const float x[3], bool live, in
         const float r2 = fmaf(rx, rx, fmaf(ry, ry, rz * rz));
         const float ri = __builtin_amdgcn_rsqf(r2);
         const float ir3 = ri * ri * ri;
-        const float kq = (float)Kd[d] * ir3;                          // bare Coulomb on the ion
+        const float kq = (float)(pa.Kq * Q[d]) * ir3;                 // bare Coulomb on the ion
         g[0] += (double)(kq * rx); g[1] += (double)(kq * ry); g[2] += (double)(kq * rz);
         // Eq. (1) summand, the grain's side: -(1 + rho) e^-rho / rho^3 (x_i - r_d)
         const float rho = r2 * ri;
@@ -788,22 +791,24 @@ __device__ __forceinline__ void tail_block(T* __restrict__ X, T* __restrict__ Y,
                                            LostList lost_list)
 {
     __shared__ double red[4][kMaxDust][3];
-    __shared__ double Kd[kMaxDust];
     __shared__ unsigned int wtally[3][4];
     __shared__ unsigned int lbase;
     const int i = i0 + threadIdx.x;
     const bool live = i < pu.N;
     const uint64_t n = (uint64_t)ctl->step;
-    if (FIX) {
-        if (threadIdx.x < ds.nd) Kd[threadIdx.x] = pa.Kq * ctl->Q[threadIdx.x];
-        __syncthreads();
-    }
     T x[3], v[3], a[3];
+    unsigned long long fx[3];
     x[0] = X[i]; x[1] = Y[i]; x[2] = Z[i];
     v[0] = VX[i]; v[1] = VY[i]; v[2] = VZ[i];   // padding slots hold zeros
+    if (FIX)
+        for (int c = 0; c < 3; ++c) fx[c] = fix[c * fstride + i];
+    // the collision decision needs none of the loaded values: its Philox
+    // block runs while the loads are in flight
+    const bool collide = live && collision_decision(i, n, pu);
     if (FIX) {
+        for (int c = 0; c < 3; ++c) fix[c * fstride + i] = 0ull;   // cleared for the next step
         float xf[3] = {(float)x[0], (float)x[1], (float)x[2]}, af[3];
-        accel_from_fixed(xf, live, i, fix, fstride, pa, ds, Kd, af, red);
+        accel_from_fixed(xf, live, fx, pa, ds, ctl->Q, af, red);
         a[0] = af[0]; a[1] = af[1]; a[2] = af[2];
         if (live) {
             AX[i] = a[0]; AY[i] = a[1]; AZ[i] = a[2];
@@ -820,7 +825,7 @@ __device__ __forceinline__ void tail_block(T* __restrict__ X, T* __restrict__ Y,
     uint8_t code = kEvNone;
     if (live) {
         T y[3], w[3];
-        push_core<T>(x, v, a, i, n, pu, ds, ctl, y, w, code, coll, lost);
+        push_core<T>(x, v, a, i, n, pu, ds, ctl, collide, y, w, code, coll, lost);
         if (INL && lost) {          // new boundary ion (Appendix B), here
             double o[6];
             reinject(pu, (uint64_t)i, n, o);

@@ -25,8 +25,9 @@ constexpr double kSymMinItems = 512.0;         // fewer one-tile items: one item
 // (a few thousand ions), each tile pair is cut into its four 64-ion source
 // sub-tiles, so that a step's pair sum is not one long chain per block.  The
 // split depends on T only, so a system's sums are grouped the same way alone
-// and in a batch.
-std::vector<odk::SymItem> sym_items_of(int T)
+// and in a batch.  one_row: one target row per item at every size (a batch
+// option; it changes the FP32 partial sums that each item flushes).
+std::vector<odk::SymItem> sym_items_of(int T, bool one_row = false)
 {
     constexpr int R = odk::kSymRows;
     const double pairs = 0.5 * (double)T * (T + 1);
@@ -36,7 +37,7 @@ std::vector<odk::SymItem> sym_items_of(int T)
     for (; I + R <= T; I += R)
         for (int J0 = I; J0 < T; J0 += C) v.push_back({I, J0, std::min(J0 + C, T), R, 0, 4});
     for (; I < T; ++I) v.push_back({I, I, T, 1, 0, 4});
-    if ((double)v.size() >= kSymMinGroupedItems) return v;
+    if ((double)v.size() >= kSymMinGroupedItems && !one_row) return v;
     v.clear();
     const int C1 = (int)std::max(1.0, std::ceil(pairs / kSymItemsTarget));
     const bool sub = C1 == 1 && pairs < kSymMinItems;
@@ -51,8 +52,12 @@ std::vector<odk::SymItem> sym_items_of(int T)
     return v;
 }
 
-// Work of an item in 64-ion source sub-tiles per target row.
-inline int sym_item_cost(const odk::SymItem& a) { return (a.J1 - a.J0) * (a.st1 - a.st0); }
+// Work of an item: target rows times 64-ion source sub-tiles.
+inline long long sym_item_cost(int rows, int J0, int J1, int st0, int st1)
+{
+    return (long long)rows * (J1 - J0) * (st1 - st0);
+}
+inline long long sym_item_cost(const odk::SymItem& a) { return sym_item_cost(a.rows, a.J0, a.J1, a.st0, a.st1); }
 
 // Longest items first, so that the short ones fill the tail.
 std::vector<odk::SymItem> sym_items(int T)

@@ -175,6 +175,39 @@ def test_batch_symmetric_graph_and_oracle(B):
         say("batch member, symmetric", shadow_step(m, o, ws[1]))
 
 
+def test_batch_symmetric_queue_and_one_row(B):
+    """The symmetric batch decompositions: items pulled from the atomic queue
+    by a resident grid give the same integer totals as one block per item
+    (bit for bit); one target row per item changes only the FP32 partial sums
+    (close to the default split, and a member against the oracle)."""
+    ws = _batch_systems()
+    steps = 7
+    res = {}
+    for cfg in ((False, False), (True, False), (True, True)):
+        with B.Batch(ws) as b:
+            b.set_sym_config(*cfg)
+            c = b.sym_config()
+            assert (c["persistent"], c["one_row"]) == cfg
+            b.step(steps)
+            b.sync()
+            res[cfg] = [(*b.get_state(s)[:3], b.accelerations(s)) for s in range(len(ws))]
+            if cfg == (True, True):
+                m = B.BatchMember(b, 4)
+                say("one-row batch member, 2^16 + 600 ions", shadow_step(m, O.Oracle(ws[4]), ws[4]))
+    for s in range(len(ws)):
+        for a, r in zip(res[(True, False)][s], res[(False, False)][s]):
+            assert np.array_equal(a, r), s
+    # one row per item: the first step's accelerations differ from the
+    # grouped split's by FP32 rounding of the item sums only
+    with B.Batch(ws) as g, B.Batch(ws) as o:
+        o.set_sym_config(False, True)
+        g.step(1)
+        o.step(1)
+        for s in range(len(ws)):
+            l2, p999, _ = accel_errors(o.accelerations(s).astype(np.float64).T, g.accelerations(s).astype(np.float64).T)
+            assert l2 < 1e-6 and p999 < 3e-6, (s, l2, p999)
+
+
 @pytest.mark.parametrize("n_ions", [(1 << 16) + 600, (1 << 16) + 412, (1 << 16) + 900])
 def test_grouped_rows_sampled_parity(B, n_ions):
     """Systems large enough for items of three target rows (259 tiles: one

@@ -6,16 +6,17 @@
 //   rows == R:  when J0 == I, each row I + r first against tiles I + r .. I + R - 1,
 //               then every row I .. I + R - 1 against tiles [max(J0, I + R), J1).
 // Also checks that every item is well formed, that a grouped item starting at
-// its own rows reaches past them, and that sym_items orders the same items
-// longest first.  Exit status 0 when all hold.
+// its own rows reaches past them, that sym_items orders the same items
+// longest first, and the same coverage for the one-row split (every item one
+// target row).  Exit status 0 when all hold.
 #include <cstdio>
 #include <vector>
 
 #include "worksplit.hpp"
 
-static int check(int T)
+static int check(int T, bool one_row)
 {
-    const std::vector<odk::SymItem> items = sym_items_of(T);
+    const std::vector<odk::SymItem> items = sym_items_of(T, one_row);
     std::vector<unsigned char> seen((size_t)T * T, 0);     // bit st: sub-tile st taken
     auto take = [&](int a, int b, int st0 = 0, int st1 = 4) {
         if (a < 0 || b < a || b >= T) return false;
@@ -33,6 +34,7 @@ static int check(int T)
                         it.st1);
             return 1;
         }
+        if (one_row && R != 1) return std::printf("T=%d: a grouped item in the one-row split\n", T), 1;
         if (R == 1) {
             for (int J = it.J0; J < it.J1; ++J)
                 if (!take(it.I, J, it.st0, it.st1)) return std::printf("T=%d: pair (%d, %d) twice\n", T, it.I, J), 1;
@@ -53,7 +55,8 @@ static int check(int T)
     for (int a = 0; a < T; ++a)
         for (int b = a; b < T; ++b)
             if (seen[(size_t)a * T + b] != 0xF) return std::printf("T=%d: pair (%d, %d) missing\n", T, a, b), 1;
-    // the launch order: the same items, longest run of source tiles first
+    if (one_row) return 0;
+    // the launch order: the same items, most work first
     const std::vector<odk::SymItem> sorted = sym_items(T);
     if (sorted.size() != items.size()) return std::printf("T=%d: sorted list differs in size\n", T), 1;
     for (size_t k = 1; k < sorted.size(); ++k)
@@ -69,7 +72,7 @@ int main()
     for (int T = 1; T <= 700; ++T) Ts.push_back(T);
     for (int T : {1021, 1024, 1025, 2048, 4095, 4096, 4097}) Ts.push_back(T);
     for (int T : Ts) {
-        fails += check(T);
+        fails += check(T, false) + check(T, true);
         const std::vector<odk::SymItem> v = sym_items_of(T);
         (v.size() && v[0].rows == odk::kSymRows) ? ++grouped : ++single;
         subtiles += v.size() && v[0].st1 - v[0].st0 == 1;
