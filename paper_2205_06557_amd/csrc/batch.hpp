@@ -29,12 +29,12 @@ struct PairItem {
     int sys, i0, jb, je, split, pad_[3];
 };
 
-struct BatchCtl {
+struct alignas(128) BatchCtl {
+    unsigned int lost_seg[kSlots * kPad32];   // lost-list segment lengths (all systems), [s * kPad32]
     unsigned int queue;                 // next pair work item
     unsigned int lost_ticket;           // reinjection blocks that have finished
-    unsigned int lost_seg[kSlots];      // lost-list segment lengths (all systems)
     int status;
-    int pad2_[13];
+    int pad2_[29];
 };
 
 __device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }

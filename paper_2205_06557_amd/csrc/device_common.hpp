@@ -6,6 +6,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace odk {
@@ -31,16 +32,20 @@ constexpr double kMomScale = 4294967296.0;      // 2^32: absorbed velocity sums,
 // Counters that every block adds to are spread over kSlots addresses (slot =
 // block index mod kSlots): device-scope atomics on one address serialise, and
 // thousands of blocks adding to one word would take tens of microseconds.
+// Each slot of a counter has a 128-byte cache line of its own (the memory
+// side performs atomics on a line one at a time), so a counter's slots are
+// kPad64 (8-byte) or kPad32 (4-byte) words apart.
 constexpr int kSlots = 64;
+constexpr int kPad64 = 16, kPad32 = 32;
 
 // Layout of one system's control block (device memory, int64/double words).
-struct Ctl {
+struct alignas(128) Ctl {
     unsigned long long acc[kMaxDust][8];   // [3] absorbed count, [4..6] sum v ([0..2] stay 0)
     unsigned long long part[kSlots][kMaxDust][3];  // Eq.(1) sums, per slot (block index mod kSlots)
-    unsigned long long n_exit[kSlots];     // exits, per slot
-    unsigned long long n_coll[kSlots];     // collisions, per slot
-    unsigned int ticket_slot[kSlots];      // tail blocks of the slot that have finished
-    unsigned int lost_seg[kSlots];         // lost-list segment lengths (single system)
+    unsigned long long n_exit[kSlots][kPad64];     // exits, per slot ([s][0])
+    unsigned long long n_coll[kSlots][kPad64];     // collisions, per slot ([s][0])
+    unsigned int ticket_slot[kSlots][kPad32];      // tail blocks of the slot that have finished ([s][0])
+    unsigned int lost_seg[kSlots * kPad32];        // lost-list segment lengths (single system), [s * kPad32]
     double Q[kMaxDust];                    // charge, e
     double last[kMaxDust][16];             // [0] Q^n, [1..12] F parts (SI), [13] absorbed count
     double sums[kMaxDust][16];             // running sums over recorded steps
@@ -52,6 +57,9 @@ struct Ctl {
     unsigned int lost_ticket;              // reinjection blocks that have finished
     int pad[5];
 };
+static_assert(offsetof(Ctl, n_exit) % 128 == 0 && offsetof(Ctl, n_coll) % 128 == 0 &&
+                  offsetof(Ctl, ticket_slot) % 128 == 0 && offsetof(Ctl, lost_seg) % 128 == 0,
+              "slot counters start on cache lines");
 
 // ---------------------------------------------------------------------------
 // Philox4x64 with 10 rounds (Salmon et al., SC'11): per round two 64x64->128

@@ -640,9 +640,9 @@ __device__ __forceinline__ void accel_from_fixed(const float x[3], bool live, co
 // Ions lost in a step (absorbed or exited), as (system, ion) pairs, for the
 // reinjection kernel.  The list is cut into kSlots segments of `cap` entries;
 // block b of the tail appends its lost ions to segment b mod kSlots
-// (seg[slot] counts them), so that blocks do not all add to one counter.
+// (seg[slot * kPad32] counts them), so that blocks do not all add to one counter.
 struct LostList {
-    unsigned int* seg;       // [kSlots] segment lengths
+    unsigned int* seg;       // [kSlots * kPad32] segment lengths, one cache line each
     unsigned int* ticket;    // reinjection blocks that have finished
     int2* item;              // [kSlots * cap]
     long long cap;
@@ -690,13 +690,13 @@ __device__ void finalize_wave(const FinalArgs& f, const DustSet& ds, Ctl* __rest
             if (g == d) S[c] = from_fixed(t, kForceScale);
         }
     // event counters: one slot per lane
-    const double ne = wave_sum((double)__hip_atomic_load(&ctl->n_exit[lane], __ATOMIC_RELAXED,
+    const double ne = wave_sum((double)__hip_atomic_load(&ctl->n_exit[lane][0], __ATOMIC_RELAXED,
                                                          __HIP_MEMORY_SCOPE_AGENT));
-    const double nc = wave_sum((double)__hip_atomic_load(&ctl->n_coll[lane], __ATOMIC_RELAXED,
+    const double nc = wave_sum((double)__hip_atomic_load(&ctl->n_coll[lane][0], __ATOMIC_RELAXED,
                                                          __HIP_MEMORY_SCOPE_AGENT));
-    ctl->n_exit[lane] = 0ull;
-    ctl->n_coll[lane] = 0ull;
-    ctl->ticket_slot[lane] = 0u;
+    ctl->n_exit[lane][0] = 0ull;
+    ctl->n_coll[lane][0] = 0ull;
+    ctl->ticket_slot[lane][0] = 0u;
     // the other grains' charges Q^n for Eq. (2)
     double px = 0.0, py = 0.0, pz = 0.0;
     for (int q = 0; q < f.nd; ++q) {
@@ -855,9 +855,9 @@ __device__ __forceinline__ void tail_block(T* __restrict__ X, T* __restrict__ Y,
         const unsigned int ne = wtally[0][0] + wtally[0][1] + wtally[0][2] + wtally[0][3];
         const unsigned int nc = wtally[1][0] + wtally[1][1] + wtally[1][2] + wtally[1][3];
         const unsigned int nl = wtally[2][0] + wtally[2][1] + wtally[2][2] + wtally[2][3];
-        if (ne) atomicAdd(&ctl->n_exit[slot], (unsigned long long)ne);
-        if (nc) atomicAdd(&ctl->n_coll[slot], (unsigned long long)nc);
-        lbase = (nl && !INL) ? atomicAdd(&lost_list.seg[blockIdx.x % kSlots], nl) : 0u;
+        if (ne) atomicAdd(&ctl->n_exit[slot][0], (unsigned long long)ne);
+        if (nc) atomicAdd(&ctl->n_coll[slot][0], (unsigned long long)nc);
+        lbase = (nl && !INL) ? atomicAdd(&lost_list.seg[(blockIdx.x % kSlots) * kPad32], nl) : 0u;
     }
     if (FIX && ds.nd > 0) {
         for (int t = threadIdx.x; t < ds.nd * 3; t += blockDim.x) {
@@ -890,7 +890,7 @@ __device__ __forceinline__ void tail_block(T* __restrict__ X, T* __restrict__ Y,
             is_last = atomicAdd(&ctl->ticket, 1u) == (unsigned int)(nblk - 1);
         } else {
             const int per_slot = nblk / kSlots + (slot < nblk % kSlots ? 1 : 0);
-            if (atomicAdd(&ctl->ticket_slot[slot], 1u) == (unsigned int)(per_slot - 1))
+            if (atomicAdd(&ctl->ticket_slot[slot][0], 1u) == (unsigned int)(per_slot - 1))
                 is_last = atomicAdd(&ctl->ticket, 1u) == (unsigned int)(kSlots - 1);
         }
     }
@@ -929,7 +929,7 @@ __device__ __forceinline__ void reinject_list(LostList L, const Sys& sysp)
     __shared__ unsigned int pre[kSlots + 1];
     __shared__ int last;
     if (threadIdx.x < kSlots) {        // segment offsets of the listed ions: a wave scan
-        const unsigned int len = L.seg[threadIdx.x];
+        const unsigned int len = L.seg[threadIdx.x * kPad32];
         unsigned int inc = len;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
@@ -962,7 +962,7 @@ __device__ __forceinline__ void reinject_list(LostList L, const Sys& sysp)
     if (threadIdx.x == 0) last = atomicAdd(L.ticket, 1u) == gridDim.x - 1;
     __syncthreads();
     if (last && threadIdx.x < kSlots) {     // every block has read the lengths
-        L.seg[threadIdx.x] = 0u;
+        L.seg[threadIdx.x * kPad32] = 0u;
         if (threadIdx.x == 0) *L.ticket = 0u;
     }
 }
