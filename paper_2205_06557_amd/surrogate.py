@@ -66,6 +66,10 @@ FLAGS = W.FLAG_FIELD_DRIVEN | W.FLAG_CONFINEMENT
 BLOCK = 200        # steps per block mean in the convergence rule
 BAND = 0.02        # relative charge band of the convergence rule
 REF_LAST = 8000    # trailing steps of the reference run that give the converged charge
+# The packaged data set (written by `pack` from `generate` runs of the batched
+# solver): 896 training runs (rows 0-895 of the 2,048-input sweep, stream 11)
+# and 64 held-out inputs (stream 12) run on four random streams (13-16); N =
+# 2^14, dt = 0.01/omega_pi, 30,000 steps, targets averaged over the last 15,000.
 DATASET = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "chain8_N16384.npz")
 STUDY_X = (1.0, 5.0, 0.4, 0.1, 33.3)   # the chain of the warm-start study (0.4 r_De spacing, Mach 1)
 
@@ -115,6 +119,52 @@ def to_targets(x5, q_c, fz_n) -> np.ndarray:
 def from_targets(x5, t16):
     t16 = np.asarray(t16, dtype=np.float64)
     return t16[:N_GRAINS] * charge_scale(x5), t16[N_GRAINS:] * force_scale(x5)
+
+
+def field_and_mutual_force(x5, q_c) -> np.ndarray:
+    """Axial forces (N) on the chain's grains that follow from their charges
+    alone: the drift field's Q E (Eq. (4); E = m_i nu u / e for the field-driven
+    flow) and the bare Coulomb forces between the grains (Eq. (2)).  For time
+    averages the product of two grains' charges is taken as the product of
+    their averages (the charges fluctuate by a few per cent, so the difference
+    is of order 1e-3 of these terms)."""
+    mach, a_um, d_l, nu_w, tt = (float(v) for v in x5)
+    te = W.ev_to_kelvin(TE_EV)
+    lam = W.debye_length(te, N_INF)
+    wpi = W.ion_plasma_frequency(N_INF, W.M_ARGON)
+    cs = math.sqrt(W.KB * te / W.M_ARGON)
+    E = W.M_ARGON * nu_w * wpi * mach * cs / W.QE
+    q = np.asarray(q_c, dtype=np.float64)
+    z = (np.arange(N_GRAINS) - 3.5) * d_l * lam
+    f = q * E
+    ke = 1.0 / (4.0 * math.pi * W.EPS0)
+    for k in range(N_GRAINS):
+        for j in range(N_GRAINS):
+            if j != k:
+                r = z[k] - z[j]
+                f[k] += ke * q[k] * q[j] * r / abs(r) ** 3
+    return f
+
+
+def to_learned(X, T) -> np.ndarray:
+    """Targets as the network learns them: the charges, and of the total axial
+    force only the ion drag (Eqs. (1) and (3)), the rest being a function of the
+    charges (field_and_mutual_force).  The total is a small difference of the
+    drag and the field force, so learning it directly amplifies its noise."""
+    L = np.array(T, dtype=np.float64, copy=True)
+    for r in range(len(X)):
+        q, fz = from_targets(X[r], T[r])
+        L[r, N_GRAINS:] = (fz - field_and_mutual_force(X[r], q)) / force_scale(X[r])
+    return L
+
+
+def from_learned(X, L) -> np.ndarray:
+    """Inverse of to_learned: normalised charges and total axial forces."""
+    T = np.array(L, dtype=np.float64, copy=True)
+    for r in range(len(X)):
+        q = T[r, :N_GRAINS] * charge_scale(X[r])
+        T[r, N_GRAINS:] = L[r, N_GRAINS:] + field_and_mutual_force(X[r], q) / force_scale(X[r])
+    return T
 
 
 def oml_charge(x5) -> float:
@@ -169,7 +219,10 @@ def run_plain(X: np.ndarray, n_ions: int, steps: int, seed: int, start: str = "r
 
 
 class Surrogate:
-    """Trained network plus its normalisation; raw inputs in, physical outputs out."""
+    """Trained network plus its normalisation; raw inputs in, physical outputs
+    out.  The network learns the charges and the ion drag (to_learned); the
+    total axial force it reports adds the field and grain-grain forces of its
+    predicted charges."""
 
     def __init__(self, mlp, t_mean, t_std):
         self.mlp, self.t_mean, self.t_std = mlp, t_mean, t_std
@@ -177,12 +230,14 @@ class Surrogate:
     @classmethod
     def train(cls, X: np.ndarray, T: np.ndarray, epochs: int = 400, batch: int = 128,
               lr: float = 2e-3, lr_final: float = 2e-5, seed: int = 0):
+        """X [n, 5] inputs, T [n, 16] normalised charges and total axial forces."""
         from . import binding as B
         mlp = B.Mlp(seed)
-        mean = T.mean(axis=0)
-        std = T.std(axis=0) + 1e-12
+        L = to_learned(X, T)
+        mean = L.mean(axis=0)
+        std = L.std(axis=0) + 1e-12
         mlp.set_normalization(BOX_LO, BOX_HI, mean, std)
-        hist = mlp.train(X, T, epochs=epochs, batch=batch, lr=lr, lr_final=lr_final, seed=seed)
+        hist = mlp.train(X, L, epochs=epochs, batch=batch, lr=lr, lr_final=lr_final, seed=seed)
         s = cls(mlp, mean, std)
         s.history = hist
         return s
@@ -199,13 +254,19 @@ class Surrogate:
         mlp.set_params(z["params"])
         return cls(mlp, z["mean"], z["std"])
 
-    def predict_targets(self, X):
+    def predict_learned(self, X):
+        """(normalised charges and ion drag [n, 16], inside [n])."""
         return self.mlp.predict(X)
+
+    def predict_targets(self, X):
+        """(normalised charges and total axial forces [n, 16], inside [n])."""
+        L, inside = self.mlp.predict(X)
+        return from_learned(X, L), inside
 
     def predict(self, X):
         """(Q [n, 8] in C, F_z [n, 8] in N, inside [n]); outside the input box
         the caller must run the full method."""
-        Y, inside = self.mlp.predict(X)
+        Y, inside = self.predict_targets(X)
         Q = np.zeros((len(X), N_GRAINS))
         F = np.zeros((len(X), N_GRAINS))
         for r in range(len(X)):
@@ -385,7 +446,7 @@ def warm_start_report(ref: dict, cands: dict, block: int = BLOCK, band: float = 
 
 
 def warm_start_study(x5, n_ions: int, ref_steps: int, steps: int, sur: Surrogate, seed: int = 4,
-                     starts=("cold", "oml", "surrogate"), log=None) -> dict:
+                     starts=("cold", "oml", "surrogate"), log=None, band: float = BAND) -> dict:
     """The whole study in one process: the reference run (started at
     CHAIN_OML_RATIO times the OML charge, random stream (seed, 1)) and each
     candidate (stream (seed, 0), common to all candidates), then
@@ -402,7 +463,7 @@ def warm_start_study(x5, n_ions: int, ref_steps: int, steps: int, sur: Surrogate
         c = charge_trace(x5, n_ions, steps, seed, 0, q0, log=log)
         c.update(q0=q0, start_seconds=t)
         cands[name] = c
-    rep = warm_start_report(ref, cands)
+    rep = warm_start_report(ref, cands, band=band)
     rep.update(x=list(map(float, x5)), n_ions=int(n_ions))
     return rep
 
@@ -501,6 +562,8 @@ def evaluate(dataset: str, out: str, epochs: int, seed: int = 11) -> dict:
     res["predict_s_per_point"] = (time.time() - t2) / len(d["Xh"])
     res["inside_box"] = int(inside.sum())
     res["heldout"] = heldout_errors(P, d["Th"])
+    Pl, _ = sur.predict_learned(d["Xh"])
+    res["heldout_ion_drag"] = heldout_errors(Pl, np.stack([to_learned(d["Xh"], t) for t in d["Th"]]))
     with open(os.path.join(out, "surrogate_result.json"), "w") as f:
         json.dump(res, f, indent=1)
     print(json.dumps(res), flush=True)

@@ -155,3 +155,34 @@ def test_dtcheck_report_finds_a_time_step_bias():
     assert c04["mean_rel_diff"] == pytest.approx(-0.06, rel=0.1)     # charges are negative
     assert r["per_dt"]["0.02"]["charge"]["systematic_rms"] == pytest.approx(0.02, rel=0.2)
     assert r["per_dt"]["0.01"]["charge"]["rms_rel_diff"] == 0.0
+
+
+def test_field_and_mutual_force_of_the_chain():
+    """The charge-determined part of the grains' axial force: Coulomb's law
+    between two charged grains (Newton's third law), the drift field's Q E
+    on a lone charged grain, and nothing for uncharged grains."""
+    x5 = np.array([1.3, 4.0, 0.5, 0.0, 30.0])          # no collisions: no drift field
+    assert np.all(S.field_and_mutual_force(x5, np.zeros(8)) == 0.0)
+    q = np.zeros(8)
+    q[2], q[3] = -2e-15, -3e-15
+    f = S.field_and_mutual_force(x5, q)
+    lam = W.debye_length(W.ev_to_kelvin(1.0), 1e14)
+    coul = 8.9875517923e9 * 6e-30 / (0.5 * lam) ** 2
+    assert f[3] == pytest.approx(coul, rel=1e-9) and f[2] == pytest.approx(-coul, rel=1e-9)
+    assert abs(f.sum()) < 1e-12 * coul
+    x5 = np.array([1.3, 4.0, 0.5, 0.2, 30.0])
+    q = np.zeros(8)
+    q[5] = -4e-15
+    wpi = W.ion_plasma_frequency(1e14, W.M_ARGON)
+    cs = math.sqrt(W.KB * W.ev_to_kelvin(1.0) / W.M_ARGON)
+    E = W.M_ARGON * 0.2 * wpi * 1.3 * cs / W.QE           # E = m_i nu u / e
+    assert S.field_and_mutual_force(x5, q)[5] == pytest.approx(-4e-15 * E, rel=1e-12)
+
+
+def test_learned_targets_round_trip():
+    X = S.sweep_inputs(20, 3)
+    rng = np.random.default_rng(4)
+    T = np.concatenate([-rng.uniform(1.5, 3.0, (20, 8)), rng.uniform(-900, 900, (20, 8))], axis=1)
+    L = S.to_learned(X, T)
+    assert np.array_equal(L[:, :8], T[:, :8])
+    assert np.allclose(S.from_learned(X, L), T, rtol=1e-12, atol=1e-9)
