@@ -228,9 +228,13 @@ class Surrogate:
         self.mlp, self.t_mean, self.t_std = mlp, t_mean, t_std
 
     @classmethod
-    def train(cls, X: np.ndarray, T: np.ndarray, epochs: int = 400, batch: int = 128,
-              lr: float = 2e-3, lr_final: float = 2e-5, seed: int = 0):
-        """X [n, 5] inputs, T [n, 16] normalised charges and total axial forces."""
+    def train(cls, X: np.ndarray, T: np.ndarray, epochs: int = 600, batch: int = 128,
+              lr: float = 1e-3, lr_final: float = 2e-5, seed: int = 11):
+        """X [n, 5] inputs, T [n, 16] normalised charges and total axial forces.
+        The defaults were chosen on a validation split (the last 96 of the 896
+        packaged training runs) among 600, 1,500 and 3,000 epochs, learning
+        rates 2e-3 and 1e-3 and batches of 64 and 128: longer training fits the
+        targets' run-to-run noise and predicts worse."""
         from . import binding as B
         mlp = B.Mlp(seed)
         L = to_learned(X, T)
@@ -351,13 +355,15 @@ def heldout_errors(P: np.ndarray, Th: np.ndarray) -> dict:
 # warm start: time to converged charge (200-step block means, 2 % band)
 
 def steps_to_converge(trace: np.ndarray, q_ref: np.ndarray, block: int = BLOCK,
-                      tol: float = BAND) -> Optional[int]:
+                      tol: float = BAND, mode: str = "chain") -> Optional[int]:
     """First step count at which the mean charge of a block of `block` steps is
-    within `tol` (relative) of q_ref for every grain; trace [steps, grains]."""
+    within `tol` (relative) of q_ref; trace [steps, grains].  mode "chain": the
+    chain's mean charge (the mean over its grains); "every": every grain."""
     nb = trace.shape[0] // block
     for k in range(nb):
         m = trace[k * block:(k + 1) * block].mean(axis=0)
-        if np.all(np.abs(m / q_ref - 1.0) <= tol):
+        ok = (abs(m.mean() / q_ref.mean() - 1.0) <= tol) if mode == "chain" else np.all(np.abs(m / q_ref - 1.0) <= tol)
+        if ok:
             return (k + 1) * block
     return None
 
@@ -380,7 +386,7 @@ def charge_trace(x5, n_ions: int, steps: int, seed: int, system_id: int, q0, log
             s.step(k)
             s.sync()
             done += k
-            if log and (done % 2000 == 0 or done == steps):
+            if log:
                 log(f"  step {done}/{steps} ({time.time() - t0:.1f} s)")
         sec = (time.time() - t0) / max(steps - 1, 1)
         q = s.history()[:, :, 0].copy()
@@ -413,24 +419,44 @@ def warm_start_report(ref: dict, cands: dict, block: int = BLOCK, band: float = 
     reference run.  ref: charge_trace of a run from its own random stream,
     Q_ref = the mean of its last REF_LAST steps; cands: name -> charge_trace
     plus "q0" and "start_seconds".  A candidate has converged at the first
-    block of `block` steps whose mean charge is within `band` of Q_ref for
-    every grain; its wall time is those steps times its seconds per step, plus
-    the time to make its start."""
+    block of `block` steps whose mean chain charge (the mean over the grains)
+    is within `band` of Q_ref's; its wall time is those steps times its
+    seconds per step, plus the time to make its start.  The steps until every
+    grain's block mean is within 2, 3 and 5 % are reported too, beside the
+    converged run's own scatter of its per-grain block means (at 2^16-2^18
+    ions a grain's 200-step mean scatters by 3-6 %, the chain's by 0.5-1 %,
+    so the every-grain 2 % band is below what a converged run holds)."""
     qr = ref["q"]
     q_ref = qr[-REF_LAST:].mean(axis=0)
     half = REF_LAST // 2
     drift = float(np.max(np.abs(qr[-REF_LAST:-half].mean(axis=0) / qr[-half:].mean(axis=0) - 1.0)))
+    # the converged run's own scatter of its block means about Q_ref, over
+    # its last 2 REF_LAST steps: the chain mean, and the largest grain deviation
+    tail = qr[-2 * REF_LAST:]
+    nb = len(tail) // block
+    bm = tail[: nb * block].reshape(nb, block, -1).mean(axis=1)
+    dev = np.abs(bm / q_ref - 1.0).max(axis=1)
+    devc = np.abs(bm.mean(axis=1) / q_ref.mean() - 1.0)
     out = {"q_ref_e": (q_ref / W.QE).tolist(), "reference_steps": int(len(qr)),
            "reference_last_steps": REF_LAST, "reference_half_window_drift": drift,
+           "reference_block_dev_every_grain_median": float(np.median(dev)),
+           "reference_block_dev_every_grain_p90": float(np.percentile(dev, 90)),
+           "reference_block_dev_chain_median": float(np.median(devc)),
+           "reference_block_dev_chain_p90": float(np.percentile(devc, 90)),
            "block_steps": block, "band": band}
     for name, c in cands.items():
         tr = c["q"]
         n2 = steps_to_converge(tr, q_ref, block, band)
         r = {"initial_max_rel_err": float(np.max(np.abs(c["q0"] / q_ref - 1.0))),
-             "steps_to_5pct": steps_to_converge(tr, q_ref, block, 0.05),
-             "steps_to_3pct": steps_to_converge(tr, q_ref, block, 0.03),
-             "steps_to_band": n2, "steps_run": int(len(tr)),
+             "initial_chain_rel_err": float(abs(np.mean(c["q0"]) / q_ref.mean() - 1.0)),
+             "steps_to_band": n2,
+             "steps_every_grain_5pct": steps_to_converge(tr, q_ref, block, 0.05, "every"),
+             "steps_every_grain_3pct": steps_to_converge(tr, q_ref, block, 0.03, "every"),
+             "steps_every_grain_2pct": steps_to_converge(tr, q_ref, block, 0.02, "every"),
+             "steps_run": int(len(tr)),
              "seconds_per_step": c["seconds_per_step"], "start_seconds": c["start_seconds"],
+             "block_chain_rel_err": [float(abs(tr[k:k + block].mean() / q_ref.mean() - 1.0))
+                                     for k in range(0, len(tr) - block + 1, block)],
              "block_max_rel_err": [float(np.max(np.abs(tr[k:k + block].mean(axis=0) / q_ref - 1.0)))
                                    for k in range(0, len(tr) - block + 1, block)]}
         r["seconds_to_band"] = None if n2 is None else n2 * c["seconds_per_step"] + c["start_seconds"]

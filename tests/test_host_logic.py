@@ -186,3 +186,18 @@ def test_learned_targets_round_trip():
     L = S.to_learned(X, T)
     assert np.array_equal(L[:, :8], T[:, :8])
     assert np.allclose(S.from_learned(X, L), T, rtol=1e-12, atol=1e-9)
+
+
+def test_chain_rule_and_every_grain_rule_differ():
+    """One grain 3 % off while the chain's mean is within 2 %: converged by the
+    chain-mean rule, not by the every-grain 2 % rule; the every-grain 5 % band
+    holds from the first block."""
+    q_ref = -np.full(8, 1000.0) * W.QE
+    tr = np.tile(q_ref, (2000, 1))
+    tr[:, 3] *= 1.03
+    ref = {"q": np.tile(q_ref, (20000, 1))}
+    r = S.warm_start_report(ref, {"x": {"q": tr, "q0": tr[0], "seconds_per_step": 1e-3, "start_seconds": 0.0}})
+    assert r["x"]["steps_to_band"] == S.BLOCK
+    assert r["x"]["steps_every_grain_2pct"] is None
+    assert r["x"]["steps_every_grain_5pct"] == S.BLOCK
+    assert r["reference_block_dev_chain_median"] < 1e-12
