@@ -40,7 +40,7 @@ constexpr int kPad64 = 16, kPad32 = 32;
 
 // Layout of one system's control block (device memory, int64/double words).
 struct alignas(128) Ctl {
-    unsigned long long acc[kMaxDust][8];   // [3] absorbed count, [4..6] sum v ([0..2] stay 0)
+    unsigned long long acc[kMaxDust][8];   // [3] absorbed count, [4..6] sum v ([0..2], [7] unused)
     unsigned long long part[kSlots][kMaxDust][3];  // Eq.(1) sums, per slot (block index mod kSlots)
     unsigned long long n_exit[kSlots][kPad64];     // exits, per slot ([s][0])
     unsigned long long n_coll[kSlots][kPad64];     // collisions, per slot ([s][0])

@@ -676,24 +676,42 @@ __device__ void finalize_wave(const FinalArgs& f, const DustSet& ds, Ctl* __rest
     const int lane = threadIdx.x & 63;
     const int d = lane;
     const long long n = ctl->step;
+    // Every load is issued before its value is used, so that their latencies
+    // (atomics live beyond the per-XCD caches) overlap instead of adding up.
     const double Qn = d < f.nd ? ctl->Q[d] : 0.0;
+    const unsigned long long ex = __hip_atomic_load(&ctl->n_exit[lane][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long co = __hip_atomic_load(&ctl->n_coll[lane][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned long long acc[4] = {0ull, 0ull, 0ull, 0ull};
+    if (d < f.nd)
+        for (int c = 0; c < 4; ++c)
+            acc[c] = __hip_atomic_load(&ctl->acc[d][3 + c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     // Eq. (1) sums: slot `lane` of every grain's three words, summed over the
-    // wave (integers, so the order does not matter), cleared for the next step
+    // wave (integers, so the order does not matter), cleared for the next
+    // step; two grains' words loaded at a time
     double S[3] = {0.0, 0.0, 0.0};
-    for (int g = 0; g < f.nd; ++g)
-        for (int c = 0; c < 3; ++c) {
-            unsigned long long* q = &ctl->part[lane][g][c];
-            const unsigned long long v = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            *q = 0ull;
-            const unsigned long long t =
-                wave_sum_u64(v) + __hip_atomic_load(&ctl->acc[g][c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (g == d) S[c] = from_fixed(t, kForceScale);
+    for (int g0 = 0; g0 < f.nd; g0 += 2) {
+        unsigned long long v[2][3];
+#pragma unroll
+        for (int gg = 0; gg < 2; ++gg)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                v[gg][c] = g0 + gg < f.nd ? __hip_atomic_load(&ctl->part[lane][g0 + gg][c], __ATOMIC_RELAXED,
+                                                              __HIP_MEMORY_SCOPE_AGENT) : 0ull;
+#pragma unroll
+        for (int gg = 0; gg < 2; ++gg) {
+            const int g = g0 + gg;
+            if (g >= f.nd) break;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                ctl->part[lane][g][c] = 0ull;
+                const unsigned long long t = wave_sum_u64(v[gg][c]);
+                if (g == d) S[c] = from_fixed(t, kForceScale);
+            }
         }
+    }
     // event counters: one slot per lane
-    const double ne = wave_sum((double)__hip_atomic_load(&ctl->n_exit[lane][0], __ATOMIC_RELAXED,
-                                                         __HIP_MEMORY_SCOPE_AGENT));
-    const double nc = wave_sum((double)__hip_atomic_load(&ctl->n_coll[lane][0], __ATOMIC_RELAXED,
-                                                         __HIP_MEMORY_SCOPE_AGENT));
+    const double ne = wave_sum((double)ex);
+    const double nc = wave_sum((double)co);
     ctl->n_exit[lane][0] = 0ull;
     ctl->n_coll[lane][0] = 0ull;
     ctl->ticket_slot[lane][0] = 0u;
@@ -709,9 +727,6 @@ __device__ void finalize_wave(const FinalArgs& f, const DustSet& ds, Ctl* __rest
         px += k * rx; py += k * ry; pz += k * rz;
     }
     if (d < f.nd) {
-        unsigned long long acc[4];
-        for (int c = 0; c < 4; ++c)
-            acc[c] = __hip_atomic_load(&ctl->acc[d][3 + c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const double cntd = (double)(long long)acc[0];
         const double P0 = from_fixed(acc[1], kMomScale);
         const double P1 = from_fixed(acc[2], kMomScale);
@@ -900,21 +915,35 @@ __device__ __forceinline__ void tail_block(T* __restrict__ X, T* __restrict__ Y,
     }
 }
 
-// The tail of one system: block b handles ions [256 b, 256 b + 256).  INL:
-// lost ions are reinjected by the thread that lost them (small systems, where
-// a step is a chain of short kernels and a separate reinjection launch would
-// lengthen it; the FP64 sampling then sets the kernel's register budget),
-// else listed for reinject_kernel.
-template <typename T, bool FIX, bool INL>
-__global__ __launch_bounds__(256) void step_tail_kernel(T* __restrict__ xs, T* __restrict__ vs,
-                                                        T* __restrict__ as, unsigned long long* __restrict__ fix,
-                                                        uint8_t* __restrict__ ev, int nsplit, PairArgs pa,
-                                                        PushArgs pu, DustSet ds, FinalArgs fa,
-                                                        Ctl* __restrict__ ctl, LostList lost_list)
+// The tail of one system: block b handles ions [256 b, 256 b + 256); lost
+// ions are listed for reinject_kernel.  Seven waves per SIMD: the per-ion
+// path fits them without spilling (only the single finalizing wave of the
+// last block may spill a register).
+template <typename T, bool FIX>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8)))
+void step_tail_kernel(T* __restrict__ xs, T* __restrict__ vs, T* __restrict__ as,
+                      unsigned long long* __restrict__ fix, uint8_t* __restrict__ ev, int nsplit, PairArgs pa,
+                      PushArgs pu, DustSet ds, FinalArgs fa, Ctl* __restrict__ ctl, LostList lost_list)
 {
     const long long P = pu.Npad;
-    tail_block<T, FIX, INL>(xs, xs + P, xs + 2 * P, vs, vs + P, vs + 2 * P, as, as + P, as + 2 * P, 3 * P,
-                            nsplit, fix, P, ev, blockIdx.x * 256, gridDim.x, pa, pu, ds, fa, ctl, 0, lost_list);
+    tail_block<T, FIX, false>(xs, xs + P, xs + 2 * P, vs, vs + P, vs + 2 * P, as, as + P, as + 2 * P, 3 * P,
+                              nsplit, fix, P, ev, blockIdx.x * 256, gridDim.x, pa, pu, ds, fa, ctl, 0, lost_list);
+}
+
+// The same tail for small systems: lost ions are reinjected by the thread
+// that lost them, where a step is a chain of short kernels and a separate
+// reinjection launch would lengthen it (the FP64 sampling then sets the
+// kernel's register budget).
+template <typename T, bool FIX>
+__global__ __launch_bounds__(256) void step_tail_inl_kernel(T* __restrict__ xs, T* __restrict__ vs,
+                                                            T* __restrict__ as, unsigned long long* __restrict__ fix,
+                                                            uint8_t* __restrict__ ev, int nsplit, PairArgs pa,
+                                                            PushArgs pu, DustSet ds, FinalArgs fa,
+                                                            Ctl* __restrict__ ctl, LostList lost_list)
+{
+    const long long P = pu.Npad;
+    tail_block<T, FIX, true>(xs, xs + P, xs + 2 * P, vs, vs + P, vs + 2 * P, as, as + P, as + 2 * P, 3 * P,
+                             nsplit, fix, P, ev, blockIdx.x * 256, gridDim.x, pa, pu, ds, fa, ctl, 0, lost_list);
 }
 
 // Reinjection (Appendix B) of the ions the step's tail listed: a grid-stride

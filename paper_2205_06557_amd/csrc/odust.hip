@@ -582,27 +582,27 @@ od_status launch_step(od_system* s, bool timed)
                 odk::pair_forces_f64<kPairBlock, kPairTile><<<gp, kPairBlock, 0, s->stream>>>(
                     (const double*)s->x, (double*)s->a, s->pa, s->ds, s->ctl);
         } else if (k == 1 && s->sym && !s->cut && inl) {
-            odk::step_tail_kernel<float, true, true><<<gt, 256, 0, s->stream>>>(
+            odk::step_tail_inl_kernel<float, true><<<gt, 256, 0, s->stream>>>(
                 (float*)s->x, (float*)s->v, (float*)s->a, s->acc_fix, s->ev, 1, s->pa, s->pu, s->ds, s->fa,
                 s->ctl, lost);
         } else if (k == 1 && s->sym && !s->cut) {
-            odk::step_tail_kernel<float, true, false><<<gt, 256, 0, s->stream>>>(
+            odk::step_tail_kernel<float, true><<<gt, 256, 0, s->stream>>>(
                 (float*)s->x, (float*)s->v, (float*)s->a, s->acc_fix, s->ev, 1, s->pa, s->pu, s->ds, s->fa,
                 s->ctl, lost);
         } else if (k == 1 && s->prec == OD_PREC_FP32 && inl) {
-            odk::step_tail_kernel<float, false, true><<<gt, 256, 0, s->stream>>>(
+            odk::step_tail_inl_kernel<float, false><<<gt, 256, 0, s->stream>>>(
                 (float*)s->x, (float*)s->v, (float*)s->a, nullptr, s->ev, eff_split(s), s->pa, s->pu, s->ds,
                 s->fa, s->ctl, lost);
         } else if (k == 1 && s->prec == OD_PREC_FP32) {
-            odk::step_tail_kernel<float, false, false><<<gt, 256, 0, s->stream>>>(
+            odk::step_tail_kernel<float, false><<<gt, 256, 0, s->stream>>>(
                 (float*)s->x, (float*)s->v, (float*)s->a, nullptr, s->ev, eff_split(s), s->pa, s->pu, s->ds,
                 s->fa, s->ctl, lost);
         } else if (k == 1 && inl) {
-            odk::step_tail_kernel<double, false, true><<<gt, 256, 0, s->stream>>>(
+            odk::step_tail_inl_kernel<double, false><<<gt, 256, 0, s->stream>>>(
                 (double*)s->x, (double*)s->v, (double*)s->a, nullptr, s->ev, 1, s->pa, s->pu, s->ds, s->fa,
                 s->ctl, lost);
         } else if (k == 1) {
-            odk::step_tail_kernel<double, false, false><<<gt, 256, 0, s->stream>>>(
+            odk::step_tail_kernel<double, false><<<gt, 256, 0, s->stream>>>(
                 (double*)s->x, (double*)s->v, (double*)s->a, nullptr, s->ev, 1, s->pa, s->pu, s->ds, s->fa,
                 s->ctl, lost);
         } else if (inl) {

@@ -26,11 +26,11 @@ def test_pmc_summary_calibrates_with_the_copy(tmp_path):
     # the counter reads half the bytes for reads, all of them for writes
     _write_counters(f, [("__amd_rocclr_copyBuffer", "FETCH_SIZE", 131072.0),
                         ("__amd_rocclr_copyBuffer", "FETCH_SIZE", 8.0),
-                        ("void odk::step_tail_kernel<float, true, false>(...)", "FETCH_SIZE", 1000.0),
-                        ("void odk::step_tail_kernel<float, true, false>(...)", "FETCH_SIZE", 1200.0),
+                        ("void odk::step_tail_kernel<float, true>(...)", "FETCH_SIZE", 1000.0),
+                        ("void odk::step_tail_kernel<float, true>(...)", "FETCH_SIZE", 1200.0),
                         ("void odk::pair_forces_f32<256, 256>(...)", "FETCH_SIZE", 50.0)])
     _write_counters(w, [("__amd_rocclr_copyBuffer", "WRITE_SIZE", 262144.0),
-                        ("void odk::step_tail_kernel<float, true, false>(...)", "WRITE_SIZE", 512.0)])
+                        ("void odk::step_tail_kernel<float, true>(...)", "WRITE_SIZE", 512.0)])
     s = P.summarise(str(f), str(w), 1024)
     assert s["calibration"]["fetch_factor"] == pytest.approx(0.5)
     assert s["calibration"]["write_factor"] == pytest.approx(1.0)
@@ -86,10 +86,10 @@ def test_pmc_summary_maps_the_symmetric_pair_kernels(tmp_path):
     w = tmp_path / "w.csv"
     _write_counters(f, [("__amd_rocclr_copyBuffer", "FETCH_SIZE", 131072.0),
                         ("void odk::pair_sym_kernel<256>(float const*, int, int, double, ...)", "FETCH_SIZE", 4000.0),
-                        ("void odk::step_tail_kernel<float, true, false>(float*, ...)", "FETCH_SIZE", 30.0)])
+                        ("void odk::step_tail_kernel<float, true>(float*, ...)", "FETCH_SIZE", 30.0)])
     _write_counters(w, [("__amd_rocclr_copyBuffer", "WRITE_SIZE", 262144.0),
                         ("void odk::pair_sym_kernel<256>(float const*, int, int, double, ...)", "WRITE_SIZE", 9000.0),
-                        ("void odk::step_tail_kernel<float, true, false>(float*, ...)", "WRITE_SIZE", 20.0)])
+                        ("void odk::step_tail_kernel<float, true>(float*, ...)", "WRITE_SIZE", 20.0)])
     s = P.summarise(str(f), str(w), 1 << 20)
     assert s["kernels"]["pair"]["fetch_bytes"] == pytest.approx(4000.0 * 1024 / 0.5)
     assert s["kernels"]["pair"]["write_bytes"] == pytest.approx(9000.0 * 1024)
