@@ -20,7 +20,10 @@ grain, the "consistent" charging model and the time averages.
     charge Q (1 - a/r_b), r_b the distance of the upstream face.
   * "Consistent" charging (Section 2): the charge of a grain that collects
     w e per absorbed superparticle plus the electron current relaxes to the
-    floating charge where the OML ion current balances the electron current.
+    floating charge where the OML ion current balances the electron current,
+    in a drifting flow (Mach 1) and in a stationary Maxwellian with T_i = T_e;
+    with cold ions at rest the grain's well reaches the boundary and the
+    grain floats below the OML root (a property of the finite domain).
     The floating charge depends on the ion current only logarithmically, so
     a wrong ion-charge increment of 25 % or more moves it by more than the
     5 % tolerance, and w e replaced by e, or a sign error, by far more.
@@ -131,6 +134,43 @@ def test_consistent_charging_floats_at_oml_root():
     sem = blocks.std(ddof=1) / math.sqrt(len(blocks))
     assert abs(qs.mean() / root - 1.0) < 0.05, (qs.mean(), root)
     assert sem < 0.01 * abs(root)
+
+
+def _consistent_mean_charge(te_over_ti, n=20000):
+    """Mean charge (e) of a 50 um grain charging by the consistent model in a
+    flow at rest (test particles, collisionless), and the OML root."""
+    a = 50e-6
+    w = _test_particle_grain(a, 0.0, n, mode=W.CHARGE_CONSISTENT, mach=0.0)
+    w = w.with_(Ti=w.Te / te_over_ti)
+    o = O.Oracle(w)
+    o.run(4000)
+    qs = np.empty(6000)
+    for k in range(len(qs)):
+        o.step()
+        qs[k] = o.get_state()[2][0] / W.QE
+    blocks = qs.reshape(20, -1).mean(axis=1)
+    return qs.mean(), blocks.std(ddof=1) / math.sqrt(len(blocks)), _oml_root(a, w), w
+
+
+def test_consistent_charging_at_rest_floats_at_oml_root():
+    """A grain in a stationary Maxwellian (Mach 0) with T_i = T_e: the well of
+    the grain's potential at the domain boundary is shallow against the ion
+    temperature (e|phi(r_b)|/k_B T_i = 0.09), so the ions arrive as from an
+    unbounded plasma and the grain floats at the OML root (measured 1.014 of it)."""
+    q, sem, root, w = _consistent_mean_charge(1.0)
+    assert abs(q / root - 1.0) < 0.05, (q, root)
+    assert sem < 0.01 * abs(root)
+
+
+def test_consistent_charging_at_rest_with_cold_ions_reading():
+    """The same grain with T_e/T_i = 33: the well reaches the boundary
+    (e|phi(r_b)|/k_B T_i = 2.1), the fixed number of superparticles
+    concentrates in it, the boundary density and the ion current fall, and the
+    grain floats well below the OML root (1.19 of it measured): the method's
+    finite-domain property behind the Mach-1 placement of the other
+    consistent-charging pin, checked here so that a change of it is seen."""
+    q, sem, root, w = _consistent_mean_charge(33.3)
+    assert q / root > 1.10, (q, root)
 
 
 @pytest.mark.parametrize("mode,n_discard", [(W.CHARGE_CONSISTENT, 15), (W.CHARGE_GIVEN, 0),
