@@ -371,13 +371,16 @@ od_status od_batch_get_pair_kernel(od_batch* b, int32_t* kind);
  * from an atomic queue (else, the default, one block per item, which the
  * hardware dispatches in the same order).  one_row: one target tile row per
  * item for every system (else, the default, each system split as it is when
- * run alone: three rows per item from 2^16 ions on).  Scheduling does not
- * change the results (integer totals); one_row changes the FP32 partial sums
- * that each item flushes, so a system then differs from its run alone by
- * rounding.  Drops a captured graph; *n_items (may be NULL) is the length of
- * the work list. */
-od_status od_batch_set_sym_config(od_batch* b, int32_t persistent, int32_t one_row);
-od_status od_batch_get_sym_config(od_batch* b, int32_t* persistent, int32_t* one_row, int32_t* n_items);
+ * run alone: three rows per item from 2^16 ions on).  items_target: the
+ * number of work items each system's split aims at (0: the default, 65536;
+ * at most 2^24).  Scheduling does not change the results (integer totals);
+ * one_row and items_target change the FP32 partial sums that each item
+ * flushes, so a system then differs from its run alone by rounding.  Drops a
+ * captured graph.  The getter reports the target in effect and *n_items, the
+ * length of the work list (any pointer may be NULL). */
+od_status od_batch_set_sym_config(od_batch* b, int32_t persistent, int32_t one_row, int64_t items_target);
+od_status od_batch_get_sym_config(od_batch* b, int32_t* persistent, int32_t* one_row, int64_t* items_target,
+                                  int32_t* n_items);
 
 /* Times the pair phase for each candidate configuration (one-sided:
  * persistent or not, jsplit 1, 2, 4, split_max_n 2^15, 2^16; symmetric:

@@ -375,8 +375,8 @@ def _batch_lib():
                                                C.POINTER(C.c_int32)]
         L.od_batch_set_pair_kernel.argtypes = [vp, i32]
         L.od_batch_get_pair_kernel.argtypes = [vp, C.POINTER(C.c_int32)]
-        L.od_batch_set_sym_config.argtypes = [vp, i32, i32]
-        L.od_batch_get_sym_config.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+        L.od_batch_set_sym_config.argtypes = [vp, i32, i32, i64]
+        L.od_batch_get_sym_config.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), i64p,
                                               C.POINTER(C.c_int32)]
         for name in ("od_init_batch", "od_batch_set_config", "od_batch_get_config", "od_batch_autotune",
                      "od_batch_set_graph", "od_step_batch", "od_batch_sync", "od_batch_get_sizes",
@@ -507,13 +507,15 @@ class Batch:
         _check(_batch_lib().od_batch_get_pair_kernel(self._h, C.byref(k)))
         return k.value
 
-    def set_sym_config(self, persistent: bool = False, one_row: bool = False):
-        _check(_batch_lib().od_batch_set_sym_config(self._h, 1 if persistent else 0, 1 if one_row else 0))
+    def set_sym_config(self, persistent: bool = False, one_row: bool = False, items_target: int = 0):
+        _check(_batch_lib().od_batch_set_sym_config(self._h, 1 if persistent else 0, 1 if one_row else 0,
+                                                    int(items_target)))
 
     def sym_config(self):
         p, r, n = C.c_int32(0), C.c_int32(0), C.c_int32(0)
-        _check(_batch_lib().od_batch_get_sym_config(self._h, C.byref(p), C.byref(r), C.byref(n)))
-        return dict(persistent=p.value, one_row=r.value, n_items=n.value)
+        t = C.c_int64(0)
+        _check(_batch_lib().od_batch_get_sym_config(self._h, C.byref(p), C.byref(r), C.byref(t), C.byref(n)))
+        return dict(persistent=p.value, one_row=r.value, items_target=t.value, n_items=n.value)
 
     def events(self, s: int):
         N = int(self.ws[s].n_ions)

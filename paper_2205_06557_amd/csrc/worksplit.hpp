@@ -25,21 +25,22 @@ constexpr double kSymMinItems = 512.0;         // fewer one-tile items: one item
 // (a few thousand ions), each tile pair is cut into its four 64-ion source
 // sub-tiles, so that a step's pair sum is not one long chain per block.  The
 // split depends on T only, so a system's sums are grouped the same way alone
-// and in a batch.  one_row: one target row per item at every size (a batch
-// option; it changes the FP32 partial sums that each item flushes).
-std::vector<odk::SymItem> sym_items_of(int T, bool one_row = false)
+// and in a batch.  one_row: one target row per item at every size; target:
+// the number of items aimed at (batch options; both change the FP32 partial
+// sums that each item flushes).
+std::vector<odk::SymItem> sym_items_of(int T, bool one_row = false, double target = kSymItemsTarget)
 {
     constexpr int R = odk::kSymRows;
     const double pairs = 0.5 * (double)T * (T + 1);
     std::vector<odk::SymItem> v;
-    const int C = (int)std::max((double)R, std::ceil(pairs / (R * kSymItemsTarget)));
+    const int C = (int)std::max((double)R, std::ceil(pairs / (R * target)));
     int I = 0;
     for (; I + R <= T; I += R)
         for (int J0 = I; J0 < T; J0 += C) v.push_back({I, J0, std::min(J0 + C, T), R, 0, 4});
     for (; I < T; ++I) v.push_back({I, I, T, 1, 0, 4});
     if ((double)v.size() >= kSymMinGroupedItems && !one_row) return v;
     v.clear();
-    const int C1 = (int)std::max(1.0, std::ceil(pairs / kSymItemsTarget));
+    const int C1 = (int)std::max(1.0, std::ceil(pairs / target));
     const bool sub = C1 == 1 && pairs < kSymMinItems;
     for (I = 0; I < T; ++I)
         for (int J0 = I; J0 < T; J0 += C1) {

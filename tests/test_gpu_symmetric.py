@@ -187,7 +187,7 @@ def test_batch_symmetric_queue_and_one_row(B):
         with B.Batch(ws) as b:
             b.set_sym_config(*cfg)
             c = b.sym_config()
-            assert (c["persistent"], c["one_row"]) == cfg
+            assert (c["persistent"], c["one_row"]) == cfg and c["items_target"] == 65536
             b.step(steps)
             b.sync()
             res[cfg] = [(*b.get_state(s)[:3], b.accelerations(s)) for s in range(len(ws))]
@@ -197,15 +197,22 @@ def test_batch_symmetric_queue_and_one_row(B):
     for s in range(len(ws)):
         for a, r in zip(res[(True, False)][s], res[(False, False)][s]):
             assert np.array_equal(a, r), s
-    # one row per item: the first step's accelerations differ from the
-    # grouped split's by FP32 rounding of the item sums only
-    with B.Batch(ws) as g, B.Batch(ws) as o:
+    # one row per item, or fewer and longer items (a target of 512 items
+    # per system changes the 2^16 + 600-ion member's split: 22 source tiles
+    # per grouped item, too few such items, so one row of 66 tiles each):
+    # the first step's accelerations differ from the default split's by
+    # FP32 rounding of the item sums only
+    with B.Batch(ws) as g, B.Batch(ws) as o, B.Batch(ws) as t:
         o.set_sym_config(False, True)
-        g.step(1)
-        o.step(1)
+        t.set_sym_config(False, False, 512)
+        assert t.sym_config()["n_items"] < g.sym_config()["n_items"]
+        for b in (g, o, t):
+            b.step(1)
         for s in range(len(ws)):
-            l2, p999, _ = accel_errors(o.accelerations(s).astype(np.float64).T, g.accelerations(s).astype(np.float64).T)
-            assert l2 < 1e-6 and p999 < 3e-6, (s, l2, p999)
+            for b in (o, t):
+                l2, p999, _ = accel_errors(b.accelerations(s).astype(np.float64).T,
+                                           g.accelerations(s).astype(np.float64).T)
+                assert l2 < 1e-6 and p999 < 3e-6, (s, l2, p999)
 
 
 @pytest.mark.parametrize("n_ions", [(1 << 16) + 600, (1 << 16) + 412, (1 << 16) + 900])

@@ -8,15 +8,15 @@
 // Also checks that every item is well formed, that a grouped item starting at
 // its own rows reaches past them, that sym_items orders the same items
 // longest first, and the same coverage for the one-row split (every item one
-// target row).  Exit status 0 when all hold.
+// target row) and for a smaller items target.  Exit status 0 when all hold.
 #include <cstdio>
 #include <vector>
 
 #include "worksplit.hpp"
 
-static int check(int T, bool one_row)
+static int check(int T, bool one_row, double target = kSymItemsTarget)
 {
-    const std::vector<odk::SymItem> items = sym_items_of(T, one_row);
+    const std::vector<odk::SymItem> items = sym_items_of(T, one_row, target);
     std::vector<unsigned char> seen((size_t)T * T, 0);     // bit st: sub-tile st taken
     auto take = [&](int a, int b, int st0 = 0, int st1 = 4) {
         if (a < 0 || b < a || b >= T) return false;
@@ -55,7 +55,7 @@ static int check(int T, bool one_row)
     for (int a = 0; a < T; ++a)
         for (int b = a; b < T; ++b)
             if (seen[(size_t)a * T + b] != 0xF) return std::printf("T=%d: pair (%d, %d) missing\n", T, a, b), 1;
-    if (one_row) return 0;
+    if (one_row || target != kSymItemsTarget) return 0;   // the launch order is checked for the default split
     // the launch order: the same items, most work first
     const std::vector<odk::SymItem> sorted = sym_items(T);
     if (sorted.size() != items.size()) return std::printf("T=%d: sorted list differs in size\n", T), 1;
@@ -72,7 +72,7 @@ int main()
     for (int T = 1; T <= 700; ++T) Ts.push_back(T);
     for (int T : {1021, 1024, 1025, 2048, 4095, 4096, 4097}) Ts.push_back(T);
     for (int T : Ts) {
-        fails += check(T, false) + check(T, true);
+        fails += check(T, false) + check(T, true) + check(T, false, 4096.0) + check(T, true, 4096.0);
         const std::vector<odk::SymItem> v = sym_items_of(T);
         (v.size() && v[0].rows == odk::kSymRows) ? ++grouped : ++single;
         subtiles += v.size() && v[0].st1 - v[0].st0 == 1;
