@@ -456,9 +456,11 @@ def surrogate_bench(args):
                       "inside_box": int(inside.sum()), "train_s": train_s,
                       "start_charge_err_vs_reference": rep["surrogate"]["initial_max_rel_err"]},
         "warm_start": {k: {kk: rep[k][kk] for kk in ("initial_chain_rel_err", "initial_max_rel_err", "steps_to_band",
+                                                      "steps_settled_in_band", "steps_settled_3pct",
                                                       "steps_every_grain_5pct", "steps_every_grain_3pct",
                                                       "seconds_to_band", "seconds_per_step")}
                        for k in ("cold", "oml", "surrogate")},
+        "speedup_vs_cold_settled": rep.get("speedup_vs_cold_settled"),
         "reference_block_dev_chain_median": rep["reference_block_dev_chain_median"],
         "reference_block_dev_every_grain_median": rep["reference_block_dev_every_grain_median"],
         "reference_half_window_drift": rep["reference_half_window_drift"],

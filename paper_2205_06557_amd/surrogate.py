@@ -368,14 +368,35 @@ def steps_to_converge(trace: np.ndarray, q_ref: np.ndarray, block: int = BLOCK,
     return None
 
 
+def steps_to_settle(trace: np.ndarray, q_ref: np.ndarray, block: int = BLOCK, tol: float = BAND) -> Optional[int]:
+    """Step count from which every later block's mean chain charge stays within
+    `tol` of q_ref's until the end of the trace (None if the last block is
+    outside): stricter than the first block inside the band, since a run can
+    pass through the band and leave it again."""
+    nb = trace.shape[0] // block
+    last_out = -1
+    for k in range(nb):
+        m = trace[k * block:(k + 1) * block].mean()
+        if abs(m / q_ref.mean() - 1.0) > tol:
+            last_out = k
+    if last_out == nb - 1:
+        return None
+    return (last_out + 2) * block
+
+
 def charge_trace(x5, n_ions: int, steps: int, seed: int, system_id: int, q0, log=None,
-                 dt_wpi: float = DT_WPI) -> dict:
+                 dt_wpi: float = DT_WPI, state=None, keep_state: bool = False) -> dict:
     """Per-step charges (C) of one chain run from the charges q0 (C; None: Q = 0),
     read from the on-device history; {"q": [steps, 8], "seconds_per_step"}
-    (the first step, which includes the set-up, is not timed)."""
+    (the first step, which includes the set-up, is not timed).  state: an
+    (x, v, q, step) tuple from an earlier trace of the same run to continue
+    from (its ions, charges and step counter, so the random streams go on);
+    keep_state: also return the final state as "state"."""
     from . import binding as B
     w = chain_workload(x5, n_ions, steps, seed, system_id, q0, dt_wpi=dt_wpi)
     with B.System(w) as s:
+        if state is not None:
+            s.set_state(*state)
         s.set_history(steps)
         s.step(1)
         s.sync()
@@ -390,8 +411,11 @@ def charge_trace(x5, n_ions: int, steps: int, seed: int, system_id: int, q0, log
                 log(f"  step {done}/{steps} ({time.time() - t0:.1f} s)")
         sec = (time.time() - t0) / max(steps - 1, 1)
         q = s.history()[:, :, 0].copy()
+        out = {"q": q, "seconds_per_step": sec}
+        if keep_state:
+            out["state"] = s.get_state()
     assert q.shape == (steps, N_GRAINS), q.shape
-    return {"q": q, "seconds_per_step": sec}
+    return out
 
 
 def start_charges(x5, start: str, sur: Optional[Surrogate] = None):
@@ -425,7 +449,9 @@ def warm_start_report(ref: dict, cands: dict, block: int = BLOCK, band: float = 
     grain's block mean is within 2, 3 and 5 % are reported too, beside the
     converged run's own scatter of its per-grain block means (at 2^16-2^18
     ions a grain's 200-step mean scatters by 3-6 %, the chain's by 0.5-1 %,
-    so the every-grain 2 % band is below what a converged run holds)."""
+    so the every-grain 2 % band is below what a converged run holds), and
+    the step from which the chain charge stays in the band to the end of the
+    run (steps_to_settle)."""
     qr = ref["q"]
     q_ref = qr[-REF_LAST:].mean(axis=0)
     half = REF_LAST // 2
@@ -450,6 +476,8 @@ def warm_start_report(ref: dict, cands: dict, block: int = BLOCK, band: float = 
         r = {"initial_max_rel_err": float(np.max(np.abs(c["q0"] / q_ref - 1.0))),
              "initial_chain_rel_err": float(abs(np.mean(c["q0"]) / q_ref.mean() - 1.0)),
              "steps_to_band": n2,
+             "steps_settled_in_band": steps_to_settle(tr, q_ref, block, band),
+             "steps_settled_3pct": steps_to_settle(tr, q_ref, block, 0.03),
              "steps_every_grain_5pct": steps_to_converge(tr, q_ref, block, 0.05, "every"),
              "steps_every_grain_3pct": steps_to_converge(tr, q_ref, block, 0.03, "every"),
              "steps_every_grain_2pct": steps_to_converge(tr, q_ref, block, 0.02, "every"),
@@ -462,6 +490,10 @@ def warm_start_report(ref: dict, cands: dict, block: int = BLOCK, band: float = 
         r["seconds_to_band"] = None if n2 is None else n2 * c["seconds_per_step"] + c["start_seconds"]
         out[name] = r
     cold, sur = out.get("cold"), out.get("surrogate")
+    if cold and sur and cold["steps_settled_in_band"] and sur["steps_settled_in_band"]:
+        out["speedup_vs_cold_settled"] = ((cold["steps_settled_in_band"] * cold["seconds_per_step"])
+                                          / (sur["steps_settled_in_band"] * sur["seconds_per_step"]
+                                             + sur["start_seconds"]))
     if cold and sur and sur["seconds_to_band"] is not None:
         if cold["seconds_to_band"] is not None:
             out["speedup_vs_cold"] = cold["seconds_to_band"] / sur["seconds_to_band"]
@@ -571,6 +603,20 @@ def dtcheck_report(X, dts, Ts) -> dict:
     return res
 
 
+def fixed_ratio_start_errors(d: dict) -> dict:
+    """Relative charge error of the fixed start (CHAIN_OML_RATIO times the
+    isolated-grain OML charge, the data set's own initial charge) against the
+    held-out reference charges (the mean of the K runs): per grain and for the
+    chain mean.  The baseline the network's charges replace."""
+    m, K = len(d["Xh"]), d["Th"].shape[0]
+    ref = np.array([[from_targets(d["Xh"][r], d["Th"][k, r])[0] for r in range(m)] for k in range(K)]).mean(axis=0)
+    q = np.array([oml_charge(x) * CHAIN_OML_RATIO for x in d["Xh"]])
+    e = np.abs(q[:, None] / ref - 1.0)
+    ec = np.abs(q / ref.mean(axis=1) - 1.0)
+    return {"grain_median": float(np.median(e)), "grain_p90": float(np.percentile(e, 90)),
+            "chain_median": float(np.median(ec)), "chain_p90": float(np.percentile(ec, 90))}
+
+
 def evaluate(dataset: str, out: str, epochs: int, seed: int = 11) -> dict:
     """Trains on the data set's training runs and measures the errors on its
     held-out inputs; writes OUT/surrogate_result.json and the network."""
@@ -590,6 +636,7 @@ def evaluate(dataset: str, out: str, epochs: int, seed: int = 11) -> dict:
     res["heldout"] = heldout_errors(P, d["Th"])
     Pl, _ = sur.predict_learned(d["Xh"])
     res["heldout_ion_drag"] = heldout_errors(Pl, np.stack([to_learned(d["Xh"], t) for t in d["Th"]]))
+    res["fixed_ratio_start_charge_err"] = fixed_ratio_start_errors(d)
     with open(os.path.join(out, "surrogate_result.json"), "w") as f:
         json.dump(res, f, indent=1)
     print(json.dumps(res), flush=True)
@@ -632,6 +679,7 @@ def main(argv=None):
     t.add_argument("--steps", type=int, required=True)
     t.add_argument("--seed", type=int, default=4)
     t.add_argument("--out", required=True)
+    t.add_argument("--resume", default=None, help="continue the run saved in this trace file")
     r = sub.add_parser("warmstart")
     r.add_argument("--traces", nargs="+", required=True)
     r.add_argument("--out", required=True)
@@ -658,10 +706,23 @@ def main(argv=None):
         name = "ratio" if a.start == "reference" else a.start
         q0, t0 = start_charges(x5, name, sur)
         sysid = 1 if a.start == "reference" else 0
-        log(f"[surrogate] trace {a.start}: N={a.n_ions}, {a.steps} steps, stream ({a.seed}, {sysid})")
-        c = charge_trace(x5, a.n_ions, a.steps, a.seed, sysid, q0, log=log)
-        np.savez(a.out, start=a.start, q=c["q"], q0=q0, start_seconds=t0,
-                 seconds_per_step=c["seconds_per_step"], x=x5, n_ions=a.n_ions)
+        prev, state = None, None
+        if a.resume:
+            prev = np.load(a.resume)
+            assert str(prev["start"]) == a.start and int(prev["n_ions"]) == a.n_ions
+            q0, t0 = prev["q0"], float(prev["start_seconds"])
+            state = (prev["sx"], prev["sv"], prev["sq"], int(prev["sstep"]))
+        log(f"[surrogate] trace {a.start}: N={a.n_ions}, {a.steps} steps, stream ({a.seed}, {sysid})"
+            + (f", continuing {a.resume} from step {state[3]}" if state else ""))
+        c = charge_trace(x5, a.n_ions, a.steps, a.seed, sysid, q0, log=log, state=state, keep_state=True)
+        q, sec = c["q"], c["seconds_per_step"]
+        if prev is not None:       # the whole run: earlier steps first, step times weighted by steps
+            n0 = len(prev["q"])
+            sec = (float(prev["seconds_per_step"]) * n0 + sec * len(q)) / (n0 + len(q))
+            q = np.concatenate([prev["q"], q])
+        sx, sv, sq, sstep = c["state"]
+        np.savez(a.out, start=a.start, q=q, q0=q0, start_seconds=t0, seconds_per_step=sec, x=x5,
+                 n_ions=a.n_ions, sx=sx, sv=sv, sq=sq, sstep=sstep)
     else:
         ref, cands, meta = None, {}, {}
         for f in a.traces:

@@ -70,3 +70,13 @@ def test_warm_start_gains_over_cold_start(sur):
     assert n_sur is not None
     assert n_cold is None or n_sur < n_cold
     assert rep["surrogate"]["initial_chain_rel_err"] < BAND
+
+
+def test_trace_resumes_bitwise(sur):
+    """A charge trace continued from a saved state (ions, charges, step
+    counter) equals the same run made in one piece, step for step."""
+    x5, n = S.STUDY_X, 4096
+    whole = S.charge_trace(x5, n, 400, 4, 1, None)
+    first = S.charge_trace(x5, n, 200, 4, 1, None, keep_state=True)
+    rest = S.charge_trace(x5, n, 200, 4, 1, None, state=first["state"])
+    assert np.array_equal(np.concatenate([first["q"], rest["q"]]), whole["q"])
