@@ -90,7 +90,7 @@ typedef struct {
     double R;            /* cylinder radius, m                              */
     double H;            /* cylinder height, m (axis from -H/2 to +H/2)      */
     double dt;           /* time step, s                                    */
-    int64_t n_ions;      /* number of ion superparticles N (>= 2)            */
+    int64_t n_ions;      /* number of ion superparticles N, 2 .. 2^29        */
     int64_t n_discard;   /* steps excluded from the time averages           */
     uint64_t seed;       /* random stream key, word 0                       */
     uint64_t system_id;  /* random stream key, word 1                       */
@@ -126,8 +126,8 @@ typedef struct od_system od_system;
  *   dust:      n_dust grains, host, 0 <= n_dust <= OD_MAX_DUST;
  *   hip_stream: hipStream_t to run on (NULL: the default stream);
  *   allocator: NULL for hipMalloc/hipFree.
- * Errors: OD_EINVAL (N < 2, non-positive sizes or temperatures, a grain that
- * crosses the wall or overlaps another, bad mode/precision/flags),
+ * Errors: OD_EINVAL (N outside [2, 2^29], non-positive sizes or temperatures,
+ * a grain that crosses the wall or overlaps another, bad mode/precision/flags),
  * OD_ENOMEM, OD_EDEVICE (no HIP device visible, or a HIP call failed),
  * OD_ESTATE (an ion could not be placed). */
 od_status od_init_system(const od_plasma* plasma, const od_sim* sim, const od_dust* dust,

@@ -235,8 +235,9 @@ od_status check_params(const od_plasma* pl, const od_sim* sim, const od_dust* du
         return fail(OD_EINVAL, "mach and nu_in must be >= 0 and E_ext finite or NaN");
     if (!(sim->R > 0) || !(sim->H > 0) || !(sim->dt > 0))
         return fail(OD_EINVAL, "R, H and dt must be positive");
-    if (sim->n_ions < 2 || sim->n_ions > (int64_t)1 << 30)
-        return fail(OD_EINVAL, "n_ions %lld out of [2, 2^30]", (long long)sim->n_ions);
+    // 2^29 keeps every plane offset c * Npad + i (c < 3) of the kernels in int range
+    if (sim->n_ions < 2 || sim->n_ions > (int64_t)1 << 29)
+        return fail(OD_EINVAL, "n_ions %lld out of [2, 2^29]", (long long)sim->n_ions);
     if (sim->n_discard < 0) return fail(OD_EINVAL, "n_discard must be >= 0");
     if (sim->charge_mode < 0 || sim->charge_mode > 2) return fail(OD_EINVAL, "bad charge_mode");
     if (sim->precision != OD_PREC_FP32 && sim->precision != OD_PREC_FP64)

@@ -37,7 +37,7 @@ def _init(w, **over):
     return B.lib().od_init_system(C.byref(pl), C.byref(sim), dust, nd, None, None, C.byref(h))
 
 
-@pytest.mark.parametrize("over", [dict(n_ions=1), dict(dt=0.0), dict(R=-1.0), dict(charge_mode=5),
+@pytest.mark.parametrize("over", [dict(n_ions=1), dict(n_ions=(1 << 29) + 1), dict(dt=0.0), dict(R=-1.0), dict(charge_mode=5),
                                   dict(precision=3), dict(flags=64), dict(reserved=1)])
 def test_invalid_parameters_rejected(over):
     assert _init(W.single_grain_small(), **over) == B.OD_EINVAL
