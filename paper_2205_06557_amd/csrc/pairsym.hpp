@@ -42,16 +42,20 @@ namespace odk {
 // on gfx950.
 constexpr int kSymWaves = 6;
 
-// One pair term (1 + r) e^-r / r^3 for the difference d.
+// One pair term (1 + r) e^-r / r^3 for the difference d, as E / r + E with
+// E = e^-r / r^2 = 2^-(r log2(e) + log2(r^2)): the 1/r^2 factor rides in the
+// exponent, so the term takes six ordinary instructions and three
+// transcendental ones (rsq, log2, exp2), which the SIMD largely overlaps with
+// the ordinary instructions of the other rows.  A sentinel far away
+// (r ~ 1e18) gives E = 0 exactly.
 __device__ __forceinline__ float sym_f(float dx, float dy, float dz)
 {
     const float kNegLog2e = -1.4426950408889634f;
     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
     const float ri = __builtin_amdgcn_rsqf(r2);
     const float r = r2 * ri;
-    const float e = __builtin_amdgcn_exp2f(r * kNegLog2e);
-    const float ri2 = ri * ri;
-    return fmaf(ri2, ri, ri2) * e;
+    const float E = __builtin_amdgcn_exp2f(fmaf(r, kNegLog2e, -__builtin_amdgcn_logf(r2)));
+    return fmaf(E, ri, E);
 }
 
 // The screened Coulomb pair term as a functor for sym_item.
